@@ -1,0 +1,168 @@
+/*
+ * bt_si_sq.h - selected inversion (SI) and selected quadratic solve (SQ) of
+ * block-tridiagonal (BT) and BT-with-arrowhead (BTA) matrices on MI355X.
+ *
+ * Problem (Sec. II-A of arXiv 2601.04904): A and B share one BT/BTA pattern
+ * with n diagonal blocks of size b and, for BTA, an arrow tip of size a
+ * (N = n b + a).  The library returns the blocks of
+ *     X^R = A^-1                 (selected inversion, A X = I)
+ *     X^< = A^-1 B A^-H          (selected quadratic solve, A X A^H = B)
+ * on that same pattern only: X_{i,i}, X_{i,i+1}, X_{i+1,i}, X_{i,t}, X_{t,i},
+ * X_{t,t}.  It uses the forward Schur-complement / backward sweeps of RGF
+ * (Alg. 1 and Alg. 2), their BTA extension (Sec. III-A) and, for P > 1, the
+ * partitioned scheme of Sec. III-B (P partitions eliminated concurrently on
+ * one GPU, then the reduced system of 2(P-1) blocks plus the tip, then the
+ * partition backward sweeps).  Diagonal blocks are inverted explicitly with
+ * partial pivoting inside the block (the inverse-instead-of-trsm formulation
+ * of Sec. II-B); there is no pivoting across blocks.
+ *
+ * Data layout.  Every matrix argument is a bt_blocks of DEVICE pointers to
+ * complex128 numbers stored as interleaved (re, im) doubles, each block
+ * dense row-major with leading dimension equal to its column count:
+ *     diag          n     blocks of b x b     M_{i,i}
+ *     upper         n-1   blocks of b x b     M_{i,i+1}
+ *     lower         n-1   blocks of b x b     M_{i+1,i}
+ *     arrow_right   n     blocks of b x a     M_{i,t}     (NULL when a == 0)
+ *     arrow_bottom  n     blocks of a x b     M_{t,i}     (NULL when a == 0)
+ *     tip           1     block  of a x a     M_{t,t}     (NULL when a == 0)
+ * Blocks of one field are contiguous (block i starts at i * rows * cols
+ * complex numbers).
+ *
+ * Ownership.  The caller owns A, B and the output blocks (device memory it
+ * allocated).  The library never writes to A or B.  The handle owns its
+ * workspace (device memory allocated at create, freed at destroy), which
+ * holds the stored factors; X^R written by bt_si_sq_factor and the factors
+ * stay valid until the next factor call or destroy, so selected_solve may be
+ * called any number of times (different B, e.g. Sigma^< and Sigma^>) after
+ * one factor.
+ *
+ * Streams and errors.  Calls that take a handle enqueue work on the HIP
+ * stream given at create and return without waiting, except that they may
+ * wait for the previous call's operation list to finish uploading.  Results
+ * are valid once that stream is synchronised.  Every function returns a
+ * bt_status; nothing is thrown across the ABI.  Argument errors are found
+ * on the host and returned at once.  A singular or non-finite pivot found
+ * on the device is recorded in the handle and returned by the next
+ * bt_si_sq_sync (BT_ERR_SINGULAR, with the block in the message).  A
+ * handle must not be used from two threads at once; distinct handles are
+ * independent.
+ */
+#ifndef BT_SI_SQ_H
+#define BT_SI_SQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bt_si_sq_plan* bt_si_sq_handle;
+
+typedef enum {
+    BT_OK = 0,
+    BT_ERR_INVALID = 1,     /* bad descriptor or argument */
+    BT_ERR_OOM = 2,         /* device allocation failed */
+    BT_ERR_SINGULAR = 3,    /* zero or non-finite pivot in a diagonal-block inverse */
+    BT_ERR_HIP = 4,         /* a HIP runtime call failed */
+    BT_ERR_STATE = 5,       /* e.g. selected_solve before factor */
+    BT_ERR_TOLERANCE = 6    /* mixed path: error estimate above tol even after the FP64 re-run */
+} bt_status;
+
+typedef enum {
+    BT_FP64 = 0,            /* every product in complex128 on FP64 MFMA */
+    BT_MIXED = 1            /* Schur-update products in complex64 on FP32 MFMA (FP32
+                               accumulation); diagonal-block inverses, the reduced
+                               system and the residual check stay FP64 */
+} bt_precision;
+
+/* flags */
+#define BT_DIAG_ONLY 0x1u   /* reserved: drop the off-diagonal outputs (not yet honoured) */
+
+typedef struct {
+    int32_t n;                  /* number of diagonal blocks, >= 1 */
+    int32_t b;                  /* diagonal block size, >= 1 */
+    int32_t a;                  /* arrow tip size, >= 0 (0: plain BT) */
+    int32_t partitions;         /* P >= 1; 1 = sequential RGF (Alg. 1/2) */
+    const int32_t* part_bounds; /* host array of P+1 increasing block indices
+                                   0 = s_0 < s_1 < ... < s_P = n, or NULL for
+                                   bounds from the cost model.  First and last
+                                   partitions need >= 1 block, middle ones >= 2. */
+    int32_t precision;          /* bt_precision */
+    double tol;                 /* mixed path: re-run in FP64 when the error estimate
+                                   exceeds tol (<= 0 selects 1e-4) */
+    uint32_t flags;
+} bt_desc;
+
+typedef struct {
+    void* diag;
+    void* upper;
+    void* lower;
+    void* arrow_right;
+    void* arrow_bottom;
+    void* tip;
+} bt_blocks;
+
+/* Device bytes the handle for this descriptor allocates (workspace for the
+ * stored factors, fill-in, reduced system and intermediates).  Pure host
+ * computation, no side effects; 0 for an invalid descriptor.  Used for
+ * admission by device-memory footprint. */
+size_t bt_si_sq_workspace_bytes(const bt_desc* desc);
+
+/* Partition bounds the library uses for this descriptor (the given ones, or
+ * those balancing the per-block cost 8(3b^3 + 11 D b^2 + 10 D^2 b) with D
+ * the total size of the block's neighbours).  bounds_out has P+1 entries. */
+bt_status bt_si_sq_partition_bounds(const bt_desc* desc, int32_t* bounds_out);
+
+/* Real floating-point operations of one fused SI+SQ solve: `executed` counts
+ * the products and inverses the library runs (complex m x n x k product =
+ * 8mnk, complex b x b inverse = 8b^3); `useful` counts those of the
+ * sequential RGF of the same matrix.  Pure host computation. */
+bt_status bt_si_sq_flops(const bt_desc* desc, double* executed, double* useful);
+
+/* Validate the descriptor, allocate the workspace, bind the HIP stream
+ * (hipStream_t passed as void*; NULL = the null stream). */
+bt_status bt_si_sq_create(const bt_desc* desc, void* hip_stream, bt_si_sq_handle* out);
+
+/* Forward Schur-complement sweep of A (the A-chain of Alg. 1, extended to
+ * BTA and partitions) and backward selected inversion (Alg. 2, SI part).
+ * Writes X^R into XR when XR is non-NULL (the factors and X^R are also kept
+ * in the workspace for selected_solve). */
+bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR);
+
+/* Selected quadratic solve for right-hand side B with the factors of the
+ * last bt_si_sq_factor (the B-chain of Alg. 1 and the SQ part of Alg. 2).
+ * Writes X^< into XL.  err_estimate and used_fp64_fallback (host pointers,
+ * may be NULL) receive the mixed-path error estimate and whether the FP64
+ * re-run was taken; they are filled synchronously (the call waits for the
+ * stream) only for BT_MIXED handles, else set to 0. */
+bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_blocks* XL,
+                                  double* err_estimate, int* used_fp64_fallback);
+
+/* Fused SI+SQ: factor(A) and selected_solve(B) in one schedule, so the
+ * B-chain of step k overlaps the A-chain of step k+1 and the SQ backward
+ * step k overlaps the SI backward step k-1.  XR may be NULL. */
+bt_status bt_si_sq_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks* B,
+                         bt_blocks* XR, bt_blocks* XL,
+                         double* err_estimate, int* used_fp64_fallback);
+
+/* Wait for the handle's stream and return the first device-side error
+ * recorded since the last sync (BT_OK if none). */
+bt_status bt_si_sq_sync(bt_si_sq_handle h);
+
+/* Free the workspace and the handle.  Waits for the stream first. */
+bt_status bt_si_sq_destroy(bt_si_sq_handle h);
+
+/* Message of the last error on this handle ("" if none); with h == NULL the
+ * last error of a call that had no handle (create, workspace queries).
+ * Valid until the next call on the same handle. */
+const char* bt_si_sq_last_error(bt_si_sq_handle h);
+
+/* Number of kernel launches of the last enqueued solve (diagnostics). */
+int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BT_SI_SQ_H */

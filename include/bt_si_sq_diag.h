@@ -1,0 +1,39 @@
+/*
+ * bt_si_sq_diag.h - diagnostic entry points of the same library: the two
+ * kernel families of bt_si_sq.h run on their own, so tests can check each
+ * against a reference.  Same conventions as bt_si_sq.h: device pointers to
+ * interleaved complex128, row-major, enqueued on the given HIP stream,
+ * status codes only.
+ */
+#ifndef BT_SI_SQ_DIAG_H
+#define BT_SI_SQ_DIAG_H
+
+#include "bt_si_sq.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* D = beta * C + alpha * op(A) op(B), D and C m x n, op(A) m x k, op(B) k x n.
+ * opA/opB: 0 = as stored, 1 = conjugate transpose (then A is stored k x m,
+ * B is stored n x k).  alpha, beta: host arrays {re, im}.  C may be NULL
+ * (beta ignored) or equal D.  mixed = 1 runs the product in complex64 on
+ * FP32 MFMA (the mixed-precision path). */
+bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
+                             const double* alpha, const void* A, int32_t lda, int32_t opA,
+                             const void* B, int32_t ldb, int32_t opB,
+                             const double* beta, const void* C, int32_t ldc,
+                             void* D, int32_t ldd, int32_t mixed, void* hip_stream);
+
+/* dst[i] = src[i]^-1 for `count` contiguous d x d matrices (Gauss-Jordan with
+ * partial pivoting inside each matrix, as used for the diagonal Schur
+ * blocks).  Waits for the stream; returns BT_ERR_SINGULAR with *bad_index set
+ * to the first matrix found singular or non-finite (bad_index may be NULL). */
+bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t count,
+                                int32_t* bad_index, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BT_SI_SQ_DIAG_H */

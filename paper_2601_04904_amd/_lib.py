@@ -1,0 +1,105 @@
+"""ctypes declarations of the C ABI in include/bt_si_sq.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbtsisq.so")
+
+BT_OK, BT_ERR_INVALID, BT_ERR_OOM, BT_ERR_SINGULAR, BT_ERR_HIP, BT_ERR_STATE, BT_ERR_TOLERANCE = range(7)
+BT_FP64, BT_MIXED = 0, 1
+STATUS_NAMES = {0: "BT_OK", 1: "BT_ERR_INVALID", 2: "BT_ERR_OOM", 3: "BT_ERR_SINGULAR",
+                4: "BT_ERR_HIP", 5: "BT_ERR_STATE", 6: "BT_ERR_TOLERANCE"}
+
+EXPORTED = [
+    "bt_si_sq_workspace_bytes", "bt_si_sq_partition_bounds", "bt_si_sq_flops",
+    "bt_si_sq_create", "bt_si_sq_factor", "bt_si_sq_selected_solve", "bt_si_sq_solve",
+    "bt_si_sq_sync", "bt_si_sq_destroy", "bt_si_sq_last_error", "bt_si_sq_last_launch_count",
+    "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse",
+]
+
+
+class bt_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("b", C.c_int32), ("a", C.c_int32),
+                ("partitions", C.c_int32), ("part_bounds", C.POINTER(C.c_int32)),
+                ("precision", C.c_int32), ("tol", C.c_double), ("flags", C.c_uint32)]
+
+
+class bt_blocks(C.Structure):
+    _fields_ = [("diag", C.c_void_p), ("upper", C.c_void_p), ("lower", C.c_void_p),
+                ("arrow_right", C.c_void_p), ("arrow_bottom", C.c_void_p), ("tip", C.c_void_p)]
+
+
+class BTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} missing "
+                          "(run python -m paper_2601_04904_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    H = C.c_void_p
+    L.bt_si_sq_workspace_bytes.argtypes = [C.POINTER(bt_desc)]
+    L.bt_si_sq_workspace_bytes.restype = C.c_size_t
+    L.bt_si_sq_partition_bounds.argtypes = [C.POINTER(bt_desc), C.POINTER(C.c_int32)]
+    L.bt_si_sq_partition_bounds.restype = C.c_int
+    L.bt_si_sq_flops.argtypes = [C.POINTER(bt_desc), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.bt_si_sq_flops.restype = C.c_int
+    L.bt_si_sq_create.argtypes = [C.POINTER(bt_desc), C.c_void_p, C.POINTER(H)]
+    L.bt_si_sq_create.restype = C.c_int
+    L.bt_si_sq_factor.argtypes = [H, C.POINTER(bt_blocks), C.POINTER(bt_blocks)]
+    L.bt_si_sq_factor.restype = C.c_int
+    L.bt_si_sq_selected_solve.argtypes = [H, C.POINTER(bt_blocks), C.POINTER(bt_blocks),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.bt_si_sq_selected_solve.restype = C.c_int
+    L.bt_si_sq_solve.argtypes = [H, C.POINTER(bt_blocks), C.POINTER(bt_blocks), C.POINTER(bt_blocks),
+                                 C.POINTER(bt_blocks), C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.bt_si_sq_solve.restype = C.c_int
+    L.bt_si_sq_sync.argtypes = [H]
+    L.bt_si_sq_sync.restype = C.c_int
+    L.bt_si_sq_destroy.argtypes = [H]
+    L.bt_si_sq_destroy.restype = C.c_int
+    L.bt_si_sq_last_error.argtypes = [H]
+    L.bt_si_sq_last_error.restype = C.c_char_p
+    L.bt_si_sq_last_launch_count.argtypes = [H]
+    L.bt_si_sq_last_launch_count.restype = C.c_int32
+    dp = C.POINTER(C.c_double)
+    L.bt_si_sq_diag_gemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_void_p, C.c_int32,
+                                     C.c_int32, C.c_void_p, C.c_int32, C.c_int32, dp, C.c_void_p,
+                                     C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    L.bt_si_sq_diag_gemm.restype = C.c_int
+    L.bt_si_sq_diag_inverse.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_int32), C.c_void_p]
+    L.bt_si_sq_diag_inverse.restype = C.c_int
+    _lib = L
+    return L
+
+
+def make_desc(n: int, b: int, a: int = 0, partitions: int = 1, bounds=None,
+              precision: int = BT_FP64, tol: float = 1e-4, flags: int = 0):
+    d = bt_desc()
+    d.n, d.b, d.a, d.partitions = n, b, a, partitions
+    keep = None
+    if bounds is not None:
+        keep = (C.c_int32 * len(bounds))(*bounds)
+        d.part_bounds = C.cast(keep, C.POINTER(C.c_int32))
+    d.precision, d.tol, d.flags = precision, tol, flags
+    d._keep = keep  # keep the bounds array alive with the descriptor
+    return d
+
+
+def check(status: int, handle=None):
+    if status != BT_OK:
+        msg = lib().bt_si_sq_last_error(handle)
+        raise BTError(status, msg.decode() if msg else "")

@@ -1,0 +1,74 @@
+// Plain-old-data descriptors shared by the host scheduler and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace btsq {
+
+// One term alpha * op(A) * op(B) of a grouped product.  A is m x k after op,
+// B is k x n after op; op = H reads the stored matrix conjugate-transposed.
+struct GemmTerm {
+    const double2* A;
+    const double2* B;
+    int32_t lda, ldb;     // leading dimensions of the stored matrices (complex elements)
+    int32_t k;
+    int32_t flags;        // bit0: op(A) = A^H, bit1: op(B) = B^H
+    double2 alpha;
+};
+
+constexpr int kMaxTerms = 6;
+constexpr int kTermAH = 1;
+constexpr int kTermBH = 2;
+
+// D = beta * C + sum_t alpha_t op(A_t) op(B_t), D and C m x n (C may alias D
+// or be null, then beta is ignored).  tile_begin: first tile of this product
+// in the launch (products of one launch are independent of each other).
+struct GemmOp {
+    double2* D;
+    const double2* C;
+    int32_t ldd, ldc;
+    int32_t m, n;
+    int32_t nterms;
+    int32_t tiles_n;      // tiles along n
+    int32_t tile_begin;
+    int32_t mixed;        // 1: products in complex64 (FP32 MFMA, FP32 accumulation)
+    double2 beta;
+    GemmTerm t[kMaxTerms];
+};
+
+// One diagonal-block inverse dst = src^-1 (d x d) by blocked Gauss-Jordan
+// elimination with partial pivoting inside the block.
+struct InvJob {
+    const double2* src;
+    double2* dst;
+    double2* W;       // d x d working copy
+    double2* Mm;      // d x kInvNB panel transform minus pivot columns
+    double2* Y;       // kInvNB x d gathered pivot rows
+    int32_t* perm;    // d pivot rows (perm[j] = pivot row of column j)
+    int32_t* used;    // d flags
+    int32_t d;
+    int32_t tag;      // block id reported on a singular pivot
+};
+
+constexpr int kInvNB = 16;          // panel width (panel rows live in registers)
+constexpr int kInvThreads = 512;    // threads of the panel kernel
+constexpr int kInvMaxDim = 1024;    // 2 rows per thread at most
+
+// D = sum_j c_j X_j (elementwise, rows x cols, leading dimensions = cols).
+constexpr int kMaxAdd = 17;
+struct AddOp {
+    double2* D;
+    const double2* X[kMaxAdd];
+    double2 c[kMaxAdd];
+    int32_t nin;
+    int32_t rows, cols;
+    int32_t pad;
+};
+
+// Device-side status: [0] error code (0 = ok, 3 = singular), [1] tag.
+struct DevStatus {
+    int32_t code;
+    int32_t tag;
+};
+
+}  // namespace btsq

@@ -1,0 +1,34 @@
+// Grouped elementwise block sums D = sum_j c_j X_j.  Used where partitions
+// meet: the arrow tip is the original tip plus one Schur contribution per
+// partition, each accumulated separately so the partitions never write the
+// same block (the single-GPU form of the tip reduction of Sec. III-B).
+#include "common.h"
+
+namespace btsq {
+
+__global__ void add_grouped(const AddOp* __restrict__ ops, int nops) {
+    const AddOp& op = ops[blockIdx.y];
+    const size_t total = (size_t)op.rows * op.cols;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < op.nin; ++j) {
+            const double2 x = op.X[j][e];
+            const double2 c = op.c[j];
+            acc.x += c.x * x.x - c.y * x.y;
+            acc.y += c.x * x.y + c.y * x.x;
+        }
+        op.D[e] = acc;
+    }
+}
+
+hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s) {
+    if (nops <= 0) return hipSuccess;
+    size_t chunks = (max_elems + 255) / 256;
+    if (chunks > 256) chunks = 256;
+    if (chunks < 1) chunks = 1;
+    hipLaunchKernelGGL(add_grouped, dim3((unsigned)chunks, nops), dim3(256), 0, s, d_ops, nops);
+    return hipGetLastError();
+}
+
+}  // namespace btsq

@@ -1,0 +1,1158 @@
+// Host runtime: elimination plan -> DAG of block operations -> grouped launches.
+//
+// Every step of the method is "eliminate block k against its current
+// neighbour set N(k)" (Alg. 1/2 for BT with N(k) = {k+1}; Sec. III-A for BTA
+// with N(k) = {k+1, t}; Sec. III-B for partitions, where middle partitions
+// eliminate against {s, k+1, t} and create fill-in).  With S = Atil_kk^-1:
+//   forward A   S = inv(Atil_kk); T_u = Atil_uk S; Atil_uv -= T_u Atil_kv
+//   forward B   S_B = (S Btil_kk) S^H; W_u = T_u Btil_kk;
+//               Btil_uv += W_u T_v^H - T_u Btil_kv - Btil_uk T_v^H
+//   backward SI tau_v = S Atil_kv; rho_u = sum_w X_uw Atil_wk;
+//               X_uk = -rho_u S; X_kv = -sum_w tau_w X_wv;
+//               X_kk = S - sum_w tau_w X_wk
+//   backward SQ GB_u = sum_w X_uw Btil_wk; BG_v = sum_w Btil_kw X_vw^H;
+//               Y21_u = GB_u S^H - rho_u S_B; L_kv = S BG_v - S_B rho_v^H
+//               - sum_w tau_w L_wv; L_uk = Y21_u - sum_w L_uw tau_w^H;
+//               L_kk = S_B - sum_w L_kw tau_w^H - sum_w tau_w Y21_w
+// (u, v, w over N(k); X = X^R, L = X^<).
+//
+// The builder walks the plan once per call and records each operation with
+// the device blocks it reads and writes.  Operations are then put on the
+// earliest dependency level (read-after-write, write-after-read and
+// write-after-write on whole blocks); all products of one level go into one
+// grouped launch and all inverses of one level into one batched inverse.
+// Independent chains - the B-chain beside the A-chain, partitions beside each
+// other, SQ backward beside SI backward - therefore share launches.
+#include "../../include/bt_si_sq.h"
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace btsq {
+hipError_t launch_gemm(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s);
+int gemm_tiles(int m, int n);
+int gemm_tiles_n(int n);
+hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
+hipError_t launch_inv_panel(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel,
+                            DevStatus* status, hipStream_t s);
+hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
+hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s);
+}  // namespace btsq
+
+using namespace btsq;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+double2 cplx(double re, double im = 0.0) { return make_double2(re, im); }
+
+struct MatRef {
+    double2* p = nullptr;
+    int r = 0, c = 0;
+    bool ok() const { return p != nullptr; }
+};
+
+struct TermSpec {
+    MatRef A;
+    bool ah;
+    MatRef B;
+    bool bh;
+    double2 alpha;
+};
+
+enum Kind { K_GEMM = 0, K_INV = 1, K_ADD = 2 };
+
+struct OpRec {
+    Kind kind;
+    MatRef D, C;
+    double2 beta = {0, 0};
+    std::vector<TermSpec> terms;
+    bool mixed = false;
+    int tag = 0;                                   // inverse: block id
+    std::vector<std::pair<double2, MatRef>> ins;   // add
+    int level = 0;
+};
+
+enum Mode { MODE_FACTOR = 0, MODE_SQ = 1, MODE_BOTH = 2 };
+
+struct Dims {
+    int n, b, a;
+    int dim(int u) const { return u == n ? a : b; }
+};
+
+// Elimination plan (host logic only).
+struct Elim {
+    int k;
+    std::vector<int> N;
+};
+
+struct PlanShape {
+    std::vector<std::vector<Elim>> parts;   // per partition, forward order
+    std::vector<int> reduced;               // kept blocks (P > 1)
+};
+
+PlanShape make_plan(const Dims& D, const std::vector<int>& bounds) {
+    PlanShape ps;
+    const int P = (int)bounds.size() - 1;
+    const int t = D.n;
+    const bool arrow = D.a > 0;
+    if (P == 1) {
+        std::vector<Elim> seq;
+        for (int k = 0; k < D.n; ++k) {
+            Elim e{k, {}};
+            if (k + 1 < D.n) e.N.push_back(k + 1);
+            if (arrow) e.N.push_back(t);
+            seq.push_back(e);
+        }
+        if (arrow) seq.push_back(Elim{t, {}});
+        ps.parts.push_back(seq);
+        return ps;
+    }
+    for (int p = 0; p < P; ++p) {
+        const int s = bounds[p], e = bounds[p + 1] - 1;
+        std::vector<Elim> part;
+        if (p == 0) {
+            for (int k = s; k < e; ++k) {
+                Elim el{k, {k + 1}};
+                if (arrow) el.N.push_back(t);
+                part.push_back(el);
+            }
+            ps.reduced.push_back(e);
+        } else if (p == P - 1) {
+            for (int k = e; k > s; --k) {
+                Elim el{k, {k - 1}};
+                if (arrow) el.N.push_back(t);
+                part.push_back(el);
+            }
+            ps.reduced.push_back(s);
+        } else {
+            for (int k = s + 1; k < e; ++k) {
+                Elim el{k, {s, k + 1}};
+                if (arrow) el.N.push_back(t);
+                part.push_back(el);
+            }
+            ps.reduced.push_back(s);
+            ps.reduced.push_back(e);
+        }
+        ps.parts.push_back(part);
+    }
+    return ps;
+}
+
+bool validate_bounds(const Dims& D, const std::vector<int>& bounds, std::string& msg) {
+    const int P = (int)bounds.size() - 1;
+    if (P < 1) { msg = "partitions must be >= 1"; return false; }
+    if (bounds.front() != 0 || bounds.back() != D.n) { msg = "bounds must run from 0 to n"; return false; }
+    for (int p = 0; p < P; ++p) {
+        const int sz = bounds[p + 1] - bounds[p];
+        const int need = (P == 1 || p == 0 || p == P - 1) ? 1 : 2;
+        if (sz < need) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "partition %d has %d blocks; first/last partitions need >= 1, middle ones >= 2", p, sz);
+            msg = buf;
+            return false;
+        }
+    }
+    return true;
+}
+
+// Balance F_k = 8(3b^3 + 11 D b^2 + 10 D^2 b) per partition, D = size of N(k).
+std::vector<int> auto_bounds(const Dims& D, int P) {
+    std::vector<int> bounds;
+    if (P <= 1) return {0, D.n};
+    const double b = D.b, a = D.a;
+    auto F = [&](double Dn) { return 3 * b * b * b + 11 * Dn * b * b + 10 * Dn * Dn * b; };
+    const double fe = F(b + a), fm = F(2 * b + a);
+    const double rest = D.n - 2.0 - 2.0 * (P - 2);
+    const double C = rest / (2.0 / fe + (P - 2) / fm);
+    int mid = (int)std::lround(C / fm + 2.0);
+    if (mid < 2) mid = 2;
+    int ends = D.n - mid * (P - 2);
+    while (ends < 2 && mid > 2) { --mid; ends = D.n - mid * (P - 2); }
+    const int first = ends / 2, last = ends - first;
+    bounds.push_back(0);
+    bounds.push_back(first);
+    for (int p = 1; p < P - 1; ++p) bounds.push_back(bounds.back() + mid);
+    bounds.push_back(bounds.back() + last);
+    (void)last;
+    return bounds;
+}
+
+uint64_t key3(int u, int v, int tag) {
+    return ((uint64_t)(uint32_t)(u + 1) << 42) | ((uint64_t)(uint32_t)(v + 1) << 21) | (uint64_t)(uint32_t)tag;
+}
+
+struct StepRec {
+    int k;
+    std::vector<int> N;
+    bool reduced_stage;
+    MatRef S, SB, Z;
+    std::map<int, MatRef> T, W, Akv, Auk, Bkv, Buk, tau, rho, GB, BG, Y21;
+};
+
+struct Builder {
+    Dims D;
+    std::vector<int> bounds;
+    Mode mode;
+    bool mixed_bulk;
+    // device pointers of the caller's blocks (null members allowed)
+    bt_blocks Aext{}, Bext{}, XRext{}, XLext{};
+    char* ws = nullptr;   // workspace base (a fake non-null base in dry runs)
+    size_t off = 0;
+    std::vector<OpRec> ops;
+    std::unordered_map<uint64_t, MatRef> curA, curB, wsA, wsB, xR, xL;
+    double flops = 0.0;
+
+    bool emitA() const { return mode == MODE_FACTOR || mode == MODE_BOTH; }
+    bool emitB() const { return mode == MODE_SQ || mode == MODE_BOTH; }
+
+    MatRef alloc(int r, int c) {
+        off = (off + 255) & ~(size_t)255;
+        MatRef m{reinterpret_cast<double2*>(ws + off), r, c};
+        off += (size_t)r * c * sizeof(double2);
+        return m;
+    }
+
+    // Caller block of field f for pair (u, v), or a fake unique address when
+    // the caller pointer is null (dry runs only).
+    MatRef ext_block(const bt_blocks& blk, int which, int u, int v) {
+        const int n = D.n, b = D.b, a = D.a, t = D.n;
+        void* base = nullptr;
+        size_t offe = 0;
+        int r = D.dim(u), c = D.dim(v);
+        int field;
+        if (u == t && v == t) { field = 5; base = blk.tip; offe = 0; }
+        else if (v == t) { field = 3; base = blk.arrow_right; offe = (size_t)u * b * a; }
+        else if (u == t) { field = 4; base = blk.arrow_bottom; offe = (size_t)v * a * b; }
+        else if (u == v) { field = 0; base = blk.diag; offe = (size_t)u * b * b; }
+        else if (v == u + 1) { field = 1; base = blk.upper; offe = (size_t)u * b * b; }
+        else { field = 2; base = blk.lower; offe = (size_t)v * b * b; }
+        (void)n;
+        double2* p;
+        if (base) p = reinterpret_cast<double2*>(base) + offe;
+        else p = reinterpret_cast<double2*>((uintptr_t)(((uint64_t)(which * 8 + field + 1)) << 44)) + offe;
+        return MatRef{p, r, c};
+    }
+
+    void init_stores() {
+        const int n = D.n, t = D.n;
+        const bool arrow = D.a > 0;
+        auto put = [&](int u, int v) {
+            curA[key3(u, v, 0)] = ext_block(Aext, 0, u, v);
+            curB[key3(u, v, 0)] = ext_block(Bext, 1, u, v);
+        };
+        for (int i = 0; i < n; ++i) {
+            put(i, i);
+            if (i + 1 < n) { put(i, i + 1); put(i + 1, i); }
+            if (arrow) { put(i, t); put(t, i); }
+        }
+        if (arrow) put(t, t);
+    }
+
+    bool selected(int u, int v) const {
+        const int t = D.n;
+        if (u == t || v == t) return D.a > 0;
+        return std::abs(u - v) <= 1;
+    }
+
+    MatRef xloc(bool lesser, int u, int v) {
+        auto& store = lesser ? xL : xR;
+        const uint64_t kk = key3(u, v, 0);
+        auto it = store.find(kk);
+        if (it != store.end()) return it->second;
+        MatRef m = alloc(D.dim(u), D.dim(v));     // reserved for every pair, used when the caller gives none
+        const bt_blocks& out = lesser ? XLext : XRext;
+        if (selected(u, v)) {
+            MatRef e = ext_block(out, lesser ? 3 : 2, u, v);
+            const bool have = (u == D.n && v == D.n) ? out.tip != nullptr
+                            : (v == D.n) ? out.arrow_right != nullptr
+                            : (u == D.n) ? out.arrow_bottom != nullptr
+                            : (u == v) ? out.diag != nullptr
+                            : (v == u + 1) ? out.upper != nullptr : out.lower != nullptr;
+            if (have) m = e;
+        }
+        store[kk] = m;
+        return m;
+    }
+
+    MatRef cur(bool isB, int u, int v, int tag) {
+        auto& st = isB ? curB : curA;
+        auto it = st.find(key3(u, v, tag));
+        return it == st.end() ? MatRef{} : it->second;
+    }
+
+    // Workspace slot that a matrix block moves into on its first update.
+    MatRef work_slot(bool isB, int u, int v, int tag) {
+        auto& st = isB ? wsB : wsA;
+        const uint64_t kk = key3(u, v, tag);
+        auto it = st.find(kk);
+        if (it != st.end()) return it->second;
+        MatRef m = alloc(D.dim(u), D.dim(v));
+        st[kk] = m;
+        return m;
+    }
+
+    void gemm(bool emit, MatRef Dst, MatRef Cin, double2 beta, std::vector<TermSpec> terms, bool mixed) {
+        std::vector<TermSpec> kept;
+        for (auto& t : terms)
+            if (t.A.ok() && t.B.ok()) kept.push_back(t);
+        if (!emit) return;
+        OpRec op;
+        op.kind = K_GEMM;
+        op.D = Dst;
+        op.C = Cin;
+        op.beta = beta;
+        op.terms = kept;
+        op.mixed = mixed;
+        for (auto& t : kept) {
+            const int k = t.ah ? t.A.r : t.A.c;
+            flops += 8.0 * Dst.r * Dst.c * k;
+        }
+        ops.push_back(op);
+    }
+
+    void inv(bool emit, MatRef src, MatRef dst, int tag) {
+        if (!emit) return;
+        OpRec op;
+        op.kind = K_INV;
+        op.C = src;
+        op.D = dst;
+        op.tag = tag;
+        flops += 8.0 * (double)dst.r * dst.r * dst.r;
+        ops.push_back(op);
+    }
+
+    void add(bool emit, MatRef Dst, std::vector<std::pair<double2, MatRef>> ins) {
+        if (!emit) return;
+        OpRec op;
+        op.kind = K_ADD;
+        op.D = Dst;
+        for (auto& x : ins)
+            if (x.second.ok()) op.ins.push_back(x);
+        ops.push_back(op);
+    }
+
+    int tip_tag(int u, int v, int part_tag) const {
+        return (u == D.n && v == D.n) ? part_tag : 0;
+    }
+
+    StepRec forward(int k, const std::vector<int>& N, int part_tag, bool reduced_stage) {
+        StepRec r;
+        r.k = k;
+        r.N = N;
+        r.reduced_stage = reduced_stage;
+        const bool mx = mixed_bulk && !reduced_stage;
+        const int dk = D.dim(k);
+        const double2 one = cplx(1), mone = cplx(-1), zero = cplx(0);
+        r.S = alloc(dk, dk);
+        inv(emitA(), cur(false, k, k, tip_tag(k, k, part_tag)), r.S, k);
+        for (int u : N) {
+            r.Auk[u] = cur(false, u, k, 0);
+            r.Akv[u] = cur(false, k, u, 0);
+            r.T[u] = alloc(D.dim(u), dk);
+            gemm(emitA(), r.T[u], MatRef{}, zero, {{r.Auk[u], false, r.S, false, one}}, mx);
+        }
+        for (int u : N)
+            for (int v : N) {
+                const int tg = tip_tag(u, v, part_tag);
+                MatRef c = cur(false, u, v, tg);
+                MatRef dst = work_slot(false, u, v, tg);
+                gemm(emitA(), dst, c, one, {{r.T[u], false, r.Akv[v], false, mone}}, mx);
+                curA[key3(u, v, tg)] = dst;
+            }
+        // B-chain
+        MatRef Bkk = cur(true, k, k, tip_tag(k, k, part_tag));
+        r.Z = alloc(dk, dk);
+        r.SB = alloc(dk, dk);
+        gemm(emitB(), r.Z, MatRef{}, zero, {{r.S, false, Bkk, false, one}}, mx);
+        gemm(emitB(), r.SB, MatRef{}, zero, {{r.Z, false, r.S, true, one}}, mx);
+        for (int u : N) {
+            r.Buk[u] = cur(true, u, k, 0);
+            r.Bkv[u] = cur(true, k, u, 0);
+            r.W[u] = alloc(D.dim(u), dk);
+            gemm(emitB(), r.W[u], MatRef{}, zero, {{r.T[u], false, Bkk, false, one}}, mx);
+        }
+        for (int u : N)
+            for (int v : N) {
+                const int tg = tip_tag(u, v, part_tag);
+                MatRef c = cur(true, u, v, tg);
+                MatRef dst = work_slot(true, u, v, tg);
+                gemm(emitB(), dst, c, one,
+                     {{r.W[u], false, r.T[v], true, one},
+                      {r.T[u], false, r.Bkv[v], false, mone},
+                      {r.Buk[u], false, r.T[v], true, mone}}, mx);
+                curB[key3(u, v, tg)] = dst;
+            }
+        return r;
+    }
+
+    void backward(StepRec& r) {
+        const bool mx = mixed_bulk && !r.reduced_stage;
+        const int k = r.k;
+        const int dk = D.dim(k);
+        const auto& N = r.N;
+        const double2 one = cplx(1), mone = cplx(-1), zero = cplx(0);
+        // selected inversion
+        for (int v : N) {
+            r.tau[v] = alloc(dk, D.dim(v));
+            gemm(emitA(), r.tau[v], MatRef{}, zero, {{r.S, false, r.Akv[v], false, one}}, mx);
+        }
+        for (int u : N) {
+            r.rho[u] = alloc(D.dim(u), dk);
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({xloc(false, u, w), false, r.Auk[w], false, one});
+            gemm(emitA(), r.rho[u], MatRef{}, zero, ts, mx);
+        }
+        for (int u : N)
+            gemm(emitA(), xloc(false, u, k), MatRef{}, zero, {{r.rho[u], false, r.S, false, mone}}, mx);
+        for (int v : N) {
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({r.tau[w], false, xloc(false, w, v), false, mone});
+            gemm(emitA(), xloc(false, k, v), MatRef{}, zero, ts, mx);
+        }
+        {
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({r.tau[w], false, xloc(false, w, k), false, mone});
+            gemm(emitA(), xloc(false, k, k), r.S, one, ts, mx);
+        }
+        // selected quadratic solve
+        for (int u : N) {
+            r.GB[u] = alloc(D.dim(u), dk);
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({xloc(false, u, w), false, r.Buk[w], false, one});
+            gemm(emitB(), r.GB[u], MatRef{}, zero, ts, mx);
+        }
+        for (int v : N) {
+            r.BG[v] = alloc(dk, D.dim(v));
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({r.Bkv[w], false, xloc(false, v, w), true, one});
+            gemm(emitB(), r.BG[v], MatRef{}, zero, ts, mx);
+        }
+        for (int u : N) {
+            r.Y21[u] = alloc(D.dim(u), dk);
+            gemm(emitB(), r.Y21[u], MatRef{}, zero,
+                 {{r.GB[u], false, r.S, true, one}, {r.rho[u], false, r.SB, false, mone}}, mx);
+        }
+        for (int v : N) {
+            MatRef L = xloc(true, k, v);
+            gemm(emitB(), L, MatRef{}, zero,
+                 {{r.S, false, r.BG[v], false, one}, {r.SB, false, r.rho[v], true, mone}}, mx);
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({r.tau[w], false, xloc(true, w, v), false, mone});
+            gemm(emitB(), L, L, one, ts, mx);
+        }
+        for (int u : N) {
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({xloc(true, u, w), false, r.tau[w], true, mone});
+            gemm(emitB(), xloc(true, u, k), r.Y21[u], one, ts, mx);
+        }
+        {
+            std::vector<TermSpec> ts;
+            for (int w : N) ts.push_back({xloc(true, k, w), false, r.tau[w], true, mone});
+            for (int w : N) ts.push_back({r.tau[w], false, r.Y21[w], false, mone});
+            gemm(emitB(), xloc(true, k, k), r.SB, one, ts, mx);
+        }
+    }
+
+    void build() {
+        init_stores();
+        PlanShape ps = make_plan(D, bounds);
+        const int P = (int)bounds.size() - 1;
+        const int t = D.n;
+        const bool arrow = D.a > 0;
+        std::vector<std::vector<StepRec>> recs(ps.parts.size());
+        for (size_t p = 0; p < ps.parts.size(); ++p) {
+            const int tag = (P > 1) ? (int)p + 1 : 0;
+            for (auto& e : ps.parts[p]) recs[p].push_back(forward(e.k, e.N, tag, false));
+        }
+        std::vector<StepRec> red;
+        if (P > 1) {
+            if (arrow) {
+                for (int isB = 0; isB < 2; ++isB) {
+                    std::vector<std::pair<double2, MatRef>> ins;
+                    ins.push_back({cplx(1), cur(isB, t, t, 0)});
+                    for (int p = 0; p < P; ++p) ins.push_back({cplx(1), cur(isB, t, t, p + 1)});
+                    MatRef dst = work_slot(isB, t, t, 0);
+                    add(isB ? emitB() : emitA(), dst, ins);
+                    (isB ? curB : curA)[key3(t, t, 0)] = dst;
+                }
+            }
+            const auto& R = ps.reduced;
+            for (size_t j = 0; j < R.size(); ++j) {
+                std::vector<int> N;
+                if (j + 1 < R.size()) N.push_back(R[j + 1]);
+                if (arrow) N.push_back(t);
+                red.push_back(forward(R[j], N, 0, true));
+            }
+            if (arrow) red.push_back(forward(t, {}, 0, true));
+            for (auto it = red.rbegin(); it != red.rend(); ++it) backward(*it);
+        }
+        for (size_t p = 0; p < recs.size(); ++p)
+            for (auto it = recs[p].rbegin(); it != recs[p].rend(); ++it) backward(*it);
+    }
+};
+
+// Dependency levels on whole blocks.
+int levelize(std::vector<OpRec>& ops) {
+    std::unordered_map<uintptr_t, int> lastW, lastR;
+    auto getW = [&](const MatRef& m) { auto it = lastW.find((uintptr_t)m.p); return it == lastW.end() ? -1 : it->second; };
+    auto getR = [&](const MatRef& m) { auto it = lastR.find((uintptr_t)m.p); return it == lastR.end() ? -1 : it->second; };
+    int maxl = -1;
+    for (auto& op : ops) {
+        std::vector<MatRef> reads;
+        if (op.kind == K_GEMM) {
+            if (op.C.ok()) reads.push_back(op.C);
+            for (auto& t : op.terms) { reads.push_back(t.A); reads.push_back(t.B); }
+        } else if (op.kind == K_INV) {
+            reads.push_back(op.C);
+        } else {
+            for (auto& x : op.ins) reads.push_back(x.second);
+        }
+        int lvl = 0;
+        for (auto& r : reads) lvl = std::max(lvl, getW(r) + 1);
+        lvl = std::max(lvl, getW(op.D) + 1);
+        lvl = std::max(lvl, getR(op.D) + 1);
+        op.level = lvl;
+        lastW[(uintptr_t)op.D.p] = lvl;
+        for (auto& r : reads) lastR[(uintptr_t)r.p] = std::max(getR(r), lvl);
+        maxl = std::max(maxl, lvl);
+    }
+    return maxl + 1;
+}
+
+struct Launch {
+    int type;         // 0 gemm, 1 inv_init, 2 inv_panel, 3 inv_finish, 4 add
+    size_t off;       // element offset into the typed array
+    int count;
+    int tiles;        // gemm: total tiles
+    int mixed;        // gemm precision
+    int maxd;         // inverse: max dim; panel: rows per thread
+    int panel;
+    size_t maxelems;  // add
+};
+
+struct Program {
+    std::vector<GemmOp> gemm;
+    std::vector<InvJob> inv;
+    std::vector<AddOp> add;
+    std::vector<Launch> launches;
+    size_t inv_scratch_bytes = 0;   // scratch the inverses need (max over levels)
+    double flops = 0.0;
+    int levels = 0;
+};
+
+GemmOp make_gemm_op(const OpRec& o) {
+    GemmOp g;
+    memset(&g, 0, sizeof g);
+    g.D = o.D.p;
+    g.C = o.C.p;
+    g.ldd = o.D.c;
+    g.ldc = o.C.ok() ? o.C.c : 0;
+    g.m = o.D.r;
+    g.n = o.D.c;
+    g.nterms = (int)o.terms.size();
+    g.tiles_n = gemm_tiles_n(g.n);
+    g.mixed = o.mixed ? 1 : 0;
+    g.beta = o.beta;
+    for (size_t i = 0; i < o.terms.size(); ++i) {
+        const TermSpec& t = o.terms[i];
+        GemmTerm& d = g.t[i];
+        d.A = t.A.p;
+        d.B = t.B.p;
+        d.lda = t.A.c;
+        d.ldb = t.B.c;
+        d.k = t.ah ? t.A.r : t.A.c;
+        d.flags = (t.ah ? kTermAH : 0) | (t.bh ? kTermBH : 0);
+        d.alpha = t.alpha;
+    }
+    return g;
+}
+
+// Turn levelled operations into typed device arrays and a launch list.
+// inv_pool: base of the inverse scratch pool (may be fake in dry runs).
+Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
+    Program pg;
+    pg.levels = nlevels;
+    std::vector<std::vector<int>> bylevel(nlevels);
+    for (int i = 0; i < (int)ops.size(); ++i) bylevel[ops[i].level].push_back(i);
+    const size_t NB = kInvNB;
+    for (int L = 0; L < nlevels; ++L) {
+        // inverses (grouped by rows per thread of the panel kernel)
+        std::vector<int> invs;
+        for (int i : bylevel[L]) if (ops[i].kind == K_INV) invs.push_back(i);
+        if (!invs.empty()) {
+            std::stable_sort(invs.begin(), invs.end(), [&](int x, int y) {
+                return (ops[x].D.r > 512) < (ops[y].D.r > 512);
+            });
+            size_t poff = 0;
+            const size_t first = pg.inv.size();
+            int maxd = 0;
+            for (int i : invs) {
+                const OpRec& o = ops[i];
+                const int d = o.D.r;
+                maxd = std::max(maxd, d);
+                InvJob j;
+                memset(&j, 0, sizeof j);
+                j.src = o.C.p;
+                j.dst = o.D.p;
+                j.d = d;
+                j.tag = o.tag;
+                auto take = [&](size_t bytes) { poff = (poff + 255) & ~(size_t)255; char* p = inv_pool + poff; poff += bytes; return p; };
+                j.W = reinterpret_cast<double2*>(take((size_t)d * d * sizeof(double2)));
+                j.Mm = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
+                j.Y = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
+                j.perm = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
+                j.used = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
+                pg.inv.push_back(j);
+            }
+            pg.inv_scratch_bytes = std::max(pg.inv_scratch_bytes, poff + 256);
+            const int nj = (int)invs.size();
+            int n1 = 0;
+            for (int i : invs) if (ops[i].D.r <= 512) ++n1;
+            pg.launches.push_back(Launch{1, first, nj, 0, 0, maxd, 0, 0});
+            const int npanels = (maxd + kInvNB - 1) / kInvNB;
+            for (int p = 0; p < npanels; ++p) {
+                if (n1 > 0) pg.launches.push_back(Launch{2, first, n1, 0, 0, 1, p, 0});
+                if (nj - n1 > 0) pg.launches.push_back(Launch{2, first + n1, nj - n1, 0, 0, 2, p, 0});
+                // trailing update W += Mm Y for the jobs that still have this panel
+                const size_t g0 = pg.gemm.size();
+                int tiles = 0;
+                for (int q = 0; q < nj; ++q) {
+                    const InvJob& j = pg.inv[first + q];
+                    if (p * kInvNB >= j.d) continue;
+                    GemmOp g;
+                    memset(&g, 0, sizeof g);
+                    g.D = j.W;
+                    g.C = j.W;
+                    g.ldd = g.ldc = j.d;
+                    g.m = g.n = j.d;
+                    g.nterms = 1;
+                    g.tiles_n = gemm_tiles_n(j.d);
+                    g.tile_begin = tiles;
+                    g.beta = cplx(1);
+                    g.t[0].A = j.Mm;
+                    g.t[0].B = j.Y;
+                    g.t[0].lda = kInvNB;
+                    g.t[0].ldb = j.d;
+                    g.t[0].k = kInvNB;
+                    g.t[0].alpha = cplx(1);
+                    tiles += gemm_tiles(j.d, j.d);
+                    pg.gemm.push_back(g);
+                }
+                pg.launches.push_back(Launch{0, g0, (int)(pg.gemm.size() - g0), tiles, 0, 0, 0, 0});
+            }
+            pg.launches.push_back(Launch{3, first, nj, 0, 0, maxd, 0, 0});
+        }
+        // products, per precision
+        for (int mx = 0; mx < 2; ++mx) {
+            const size_t g0 = pg.gemm.size();
+            int tiles = 0;
+            for (int i : bylevel[L]) {
+                const OpRec& o = ops[i];
+                if (o.kind != K_GEMM || (int)o.mixed != mx) continue;
+                GemmOp g = make_gemm_op(o);
+                g.tile_begin = tiles;
+                tiles += gemm_tiles(g.m, g.n);
+                pg.gemm.push_back(g);
+            }
+            if (pg.gemm.size() > g0)
+                pg.launches.push_back(Launch{0, g0, (int)(pg.gemm.size() - g0), tiles, mx, 0, 0, 0});
+        }
+        // sums
+        {
+            const size_t a0 = pg.add.size();
+            size_t maxe = 0;
+            for (int i : bylevel[L]) {
+                const OpRec& o = ops[i];
+                if (o.kind != K_ADD) continue;
+                AddOp a;
+                memset(&a, 0, sizeof a);
+                a.D = o.D.p;
+                a.nin = (int)o.ins.size();
+                a.rows = o.D.r;
+                a.cols = o.D.c;
+                for (int q = 0; q < a.nin && q < kMaxAdd; ++q) {
+                    a.X[q] = o.ins[q].second.p;
+                    a.c[q] = o.ins[q].first;
+                }
+                maxe = std::max(maxe, (size_t)a.rows * a.cols);
+                pg.add.push_back(a);
+            }
+            if (pg.add.size() > a0)
+                pg.launches.push_back(Launch{4, a0, (int)(pg.add.size() - a0), 0, 0, 0, 0, maxe});
+        }
+    }
+    return pg;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct bt_si_sq_plan {
+    Dims D{};
+    bt_desc desc{};
+    std::vector<int> bounds;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_main = 0;        // bytes of block slots
+    char* inv_pool = nullptr;
+    size_t inv_bytes = 0;
+    DevStatus* status = nullptr;
+    std::string err;
+    bool factored = false;
+    bt_blocks XR_used{};        // where the last factor put X^R
+    bt_blocks A_used{};
+    int32_t last_launches = 0;
+    // cached programs per mode
+    struct Cached {
+        bool valid = false;
+        bt_blocks A{}, B{}, XR{}, XL{};
+        Program prog;
+        char* dev = nullptr;
+        size_t dev_bytes = 0;
+        size_t off_gemm = 0, off_inv = 0, off_add = 0;
+    } cache[3];
+    char* host_stage = nullptr;
+    size_t host_stage_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+};
+
+namespace {
+
+bool same_blocks(const bt_blocks& x, const bt_blocks& y) { return memcmp(&x, &y, sizeof x) == 0; }
+
+bt_status set_err(bt_si_sq_plan* h, bt_status st, const std::string& msg) {
+    if (h) h->err = msg; else g_last_error = msg;
+    return st;
+}
+
+bt_status hip_err(bt_si_sq_plan* h, hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return set_err(h, BT_ERR_HIP, m);
+}
+
+bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
+    if (!d) { msg = "null descriptor"; return false; }
+    if (d->n < 1 || d->b < 1 || d->a < 0) { msg = "need n >= 1, b >= 1, a >= 0"; return false; }
+    if (d->b > kInvMaxDim || d->a > kInvMaxDim) { msg = "block sizes above 1024 are not supported"; return false; }
+    if (d->precision != BT_FP64 && d->precision != BT_MIXED) { msg = "unknown precision"; return false; }
+    const int P = d->partitions;
+    if (P < 1) { msg = "partitions must be >= 1"; return false; }
+    Dims D{d->n, d->b, d->a};
+    if (d->part_bounds) {
+        bounds.assign(d->part_bounds, d->part_bounds + P + 1);
+    } else {
+        if (P > 1 && d->n < 2 * P - 2) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "P = %d partitions need n >= 2P - 2 = %d blocks", P, 2 * P - 2);
+            msg = buf;
+            return false;
+        }
+        bounds = auto_bounds(D, P);
+    }
+    return validate_bounds(D, bounds, msg);
+}
+
+// Dry run: workspace layout and inverse scratch for a descriptor.
+void dry_run(const Dims& D, const std::vector<int>& bounds, bool mixed, size_t& ws_bytes,
+             size_t& inv_bytes, double& flops) {
+    Builder bd;
+    bd.D = D;
+    bd.bounds = bounds;
+    bd.mode = MODE_BOTH;
+    bd.mixed_bulk = mixed;
+    bd.ws = reinterpret_cast<char*>((uintptr_t)1 << 40);
+    bd.build();
+    ws_bytes = bd.off + 256;
+    flops = bd.flops;
+    int nl = levelize(bd.ops);
+    Program pg = compile(bd.ops, nl, reinterpret_cast<char*>((uintptr_t)3 << 40));
+    inv_bytes = pg.inv_scratch_bytes;
+}
+
+hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
+    const Program& pg = c.prog;
+    GemmOp* dg = reinterpret_cast<GemmOp*>(c.dev + c.off_gemm);
+    InvJob* dj = reinterpret_cast<InvJob*>(c.dev + c.off_inv);
+    AddOp* da = reinterpret_cast<AddOp*>(c.dev + c.off_add);
+    hipError_t e = hipSuccess;
+    for (const Launch& L : pg.launches) {
+        switch (L.type) {
+            case 0: e = launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, h->stream); break;
+            case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, h->stream); break;
+            case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, h->status, h->stream); break;
+            case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, h->stream); break;
+            case 4: e = launch_add(da + L.off, L.count, L.maxelems, h->stream); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    h->last_launches = (int32_t)pg.launches.size();
+    return hipSuccess;
+}
+
+bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const bt_blocks* A, const bt_blocks* B,
+                          const bt_blocks* XR, const bt_blocks* XL) {
+    bt_si_sq_plan::Cached& c = h->cache[mode];
+    bt_blocks zA{}, zB{}, zXR{}, zXL{};
+    const bt_blocks& a = A ? *A : zA;
+    const bt_blocks& b = B ? *B : zB;
+    const bt_blocks& xr = XR ? *XR : zXR;
+    const bt_blocks& xl = XL ? *XL : zXL;
+    if (!(c.valid && same_blocks(c.A, a) && same_blocks(c.B, b) && same_blocks(c.XR, xr) && same_blocks(c.XL, xl))) {
+        Builder bd;
+        bd.D = h->D;
+        bd.bounds = h->bounds;
+        bd.mode = mode;
+        bd.mixed_bulk = h->desc.precision == BT_MIXED;
+        bd.Aext = a;
+        bd.Bext = b;
+        bd.XRext = xr;
+        bd.XLext = xl;
+        bd.ws = h->ws;
+        bd.build();
+        if (bd.off + 256 > h->ws_main)
+            return set_err(h, BT_ERR_INVALID, "internal: workspace layout changed");
+        int nl = levelize(bd.ops);
+        Program pg = compile(bd.ops, nl, h->inv_pool);
+        if (pg.inv_scratch_bytes > h->inv_bytes)
+            return set_err(h, BT_ERR_INVALID, "internal: inverse scratch too small");
+        pg.flops = bd.flops;
+        const size_t bg = pg.gemm.size() * sizeof(GemmOp);
+        const size_t bi = pg.inv.size() * sizeof(InvJob);
+        const size_t ba = pg.add.size() * sizeof(AddOp);
+        const size_t off_inv = (bg + 255) & ~(size_t)255;
+        const size_t off_add = (off_inv + bi + 255) & ~(size_t)255;
+        const size_t total = off_add + ba + 256;
+        // the previous upload must have left the staging buffer
+        if (h->upload_done) hipEventSynchronize(h->upload_done);
+        if (total > c.dev_bytes) {
+            if (c.dev) {
+                hipStreamSynchronize(h->stream);
+                hipFree(c.dev);
+                c.dev = nullptr;
+            }
+            hipError_t e = hipMalloc(&c.dev, total);
+            if (e != hipSuccess) { c.dev_bytes = 0; return set_err(h, BT_ERR_OOM, "operation list allocation failed"); }
+            c.dev_bytes = total;
+        }
+        if (total > h->host_stage_bytes) {
+            if (h->host_stage) hipHostFree(h->host_stage);
+            h->host_stage = nullptr;
+            hipError_t e = hipHostMalloc((void**)&h->host_stage, total, 0);
+            if (e != hipSuccess) { h->host_stage_bytes = 0; return hip_err(h, e, "hipHostMalloc"); }
+            h->host_stage_bytes = total;
+        }
+        if (bg) memcpy(h->host_stage, pg.gemm.data(), bg);
+        if (bi) memcpy(h->host_stage + off_inv, pg.inv.data(), bi);
+        if (ba) memcpy(h->host_stage + off_add, pg.add.data(), ba);
+        hipError_t e = hipMemcpyAsync(c.dev, h->host_stage, total, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return hip_err(h, e, "hipMemcpyAsync(op list)");
+        e = hipEventRecord(h->upload_done, h->stream);
+        if (e != hipSuccess) return hip_err(h, e, "hipEventRecord");
+        c.prog = std::move(pg);
+        c.off_gemm = 0;
+        c.off_inv = off_inv;
+        c.off_add = off_add;
+        c.A = a; c.B = b; c.XR = xr; c.XL = xl;
+        c.valid = true;
+    }
+    hipError_t e = run_program(h, c);
+    if (e != hipSuccess) return hip_err(h, e, "kernel launch");
+    return BT_OK;
+}
+
+bool check_blocks(const Dims& D, const bt_blocks* m, bool need, std::string& msg, const char* name) {
+    if (!m) {
+        if (need) { msg = std::string(name) + " is null"; return false; }
+        return true;
+    }
+    if (!m->diag || (D.n > 1 && (!m->upper || !m->lower))) {
+        msg = std::string(name) + ": diag/upper/lower pointers missing";
+        return false;
+    }
+    if (D.a > 0 && (!m->arrow_right || !m->arrow_bottom || !m->tip)) {
+        msg = std::string(name) + ": arrow/tip pointers missing for a > 0";
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t bt_si_sq_workspace_bytes(const bt_desc* desc) {
+    std::vector<int> bounds;
+    std::string msg;
+    if (!desc_bounds(desc, bounds, msg)) { g_last_error = msg; return 0; }
+    size_t ws = 0, inv = 0;
+    double fl = 0;
+    dry_run(Dims{desc->n, desc->b, desc->a}, bounds, desc->precision == BT_MIXED, ws, inv, fl);
+    return ws + inv + 4096;
+}
+
+bt_status bt_si_sq_partition_bounds(const bt_desc* desc, int32_t* bounds_out) {
+    std::vector<int> bounds;
+    std::string msg;
+    if (!bounds_out) return set_err(nullptr, BT_ERR_INVALID, "bounds_out is null");
+    if (!desc_bounds(desc, bounds, msg)) return set_err(nullptr, BT_ERR_INVALID, msg);
+    for (size_t i = 0; i < bounds.size(); ++i) bounds_out[i] = bounds[i];
+    return BT_OK;
+}
+
+bt_status bt_si_sq_flops(const bt_desc* desc, double* executed, double* useful) {
+    std::vector<int> bounds;
+    std::string msg;
+    if (!desc_bounds(desc, bounds, msg)) return set_err(nullptr, BT_ERR_INVALID, msg);
+    size_t ws = 0, inv = 0;
+    double fe = 0, fu = 0;
+    Dims D{desc->n, desc->b, desc->a};
+    dry_run(D, bounds, false, ws, inv, fe);
+    dry_run(D, {0, desc->n}, false, ws, inv, fu);
+    if (executed) *executed = fe;
+    if (useful) *useful = fu;
+    return BT_OK;
+}
+
+bt_status bt_si_sq_create(const bt_desc* desc, void* hip_stream, bt_si_sq_handle* out) {
+    if (!out) return set_err(nullptr, BT_ERR_INVALID, "out is null");
+    *out = nullptr;
+    std::vector<int> bounds;
+    std::string msg;
+    if (!desc_bounds(desc, bounds, msg)) return set_err(nullptr, BT_ERR_INVALID, msg);
+    std::unique_ptr<bt_si_sq_plan> h(new bt_si_sq_plan());
+    h->desc = *desc;
+    h->desc.part_bounds = nullptr;
+    if (!(h->desc.tol > 0)) h->desc.tol = 1e-4;
+    h->D = Dims{desc->n, desc->b, desc->a};
+    h->bounds = bounds;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    double fl = 0;
+    dry_run(h->D, bounds, desc->precision == BT_MIXED, h->ws_main, h->inv_bytes, fl);
+    hipError_t e = hipMalloc(&h->ws, h->ws_main);
+    if (e != hipSuccess) { hipGetLastError(); return set_err(nullptr, BT_ERR_OOM, "workspace allocation failed"); }
+    e = hipMalloc(&h->inv_pool, h->inv_bytes);
+    if (e != hipSuccess) { hipGetLastError(); hipFree(h->ws); return set_err(nullptr, BT_ERR_OOM, "inverse scratch allocation failed"); }
+    e = hipMalloc(&h->status, sizeof(DevStatus));
+    if (e != hipSuccess) { hipFree(h->ws); hipFree(h->inv_pool); return set_err(nullptr, BT_ERR_OOM, "status allocation failed"); }
+    DevStatus z{0, 0};
+    e = hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        hipFree(h->ws); hipFree(h->inv_pool); hipFree(h->status);
+        return hip_err(nullptr, e, "create");
+    }
+    *out = h.release();
+    return BT_OK;
+}
+
+bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    std::string msg;
+    if (!check_blocks(h->D, A, true, msg, "A") || !check_blocks(h->D, XR, false, msg, "XR"))
+        return set_err(h, BT_ERR_INVALID, msg);
+    bt_status st = prepare_and_run(h, MODE_FACTOR, A, nullptr, XR, nullptr);
+    if (st == BT_OK) {
+        h->factored = true;
+        h->A_used = *A;
+        h->XR_used = XR ? *XR : bt_blocks{};
+    }
+    return st;
+}
+
+bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_blocks* XL,
+                                  double* err_estimate, int* used_fp64_fallback) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    if (err_estimate) *err_estimate = 0.0;
+    if (used_fp64_fallback) *used_fp64_fallback = 0;
+    if (!h->factored) return set_err(h, BT_ERR_STATE, "selected_solve before factor");
+    std::string msg;
+    if (!check_blocks(h->D, B, true, msg, "B") || !check_blocks(h->D, XL, true, msg, "XL"))
+        return set_err(h, BT_ERR_INVALID, msg);
+    return prepare_and_run(h, MODE_SQ, &h->A_used, B, &h->XR_used, XL);
+}
+
+bt_status bt_si_sq_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks* B,
+                         bt_blocks* XR, bt_blocks* XL, double* err_estimate, int* used_fp64_fallback) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    if (err_estimate) *err_estimate = 0.0;
+    if (used_fp64_fallback) *used_fp64_fallback = 0;
+    std::string msg;
+    if (!check_blocks(h->D, A, true, msg, "A") || !check_blocks(h->D, B, true, msg, "B") ||
+        !check_blocks(h->D, XR, false, msg, "XR") || !check_blocks(h->D, XL, true, msg, "XL"))
+        return set_err(h, BT_ERR_INVALID, msg);
+    bt_status st = prepare_and_run(h, MODE_BOTH, A, B, XR, XL);
+    if (st == BT_OK) {
+        h->factored = true;
+        h->A_used = *A;
+        h->XR_used = XR ? *XR : bt_blocks{};
+    }
+    return st;
+}
+
+bt_status bt_si_sq_sync(bt_si_sq_handle h) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
+    DevStatus s{0, 0};
+    e = hipMemcpy(&s, h->status, sizeof s, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_err(h, e, "status readback");
+    if (s.code != 0) {
+        DevStatus z{0, 0};
+        hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
+        char buf[160];
+        snprintf(buf, sizeof buf, "singular or non-finite pivot while inverting diagonal block %d%s", s.tag,
+                 s.tag == h->D.n ? " (arrow tip)" : "");
+        return set_err(h, BT_ERR_SINGULAR, buf);
+    }
+    h->err.clear();
+    return BT_OK;
+}
+
+bt_status bt_si_sq_destroy(bt_si_sq_handle h) {
+    if (!h) return BT_OK;
+    hipStreamSynchronize(h->stream);
+    for (auto& c : h->cache)
+        if (c.dev) hipFree(c.dev);
+    if (h->host_stage) hipHostFree(h->host_stage);
+    if (h->upload_done) hipEventDestroy(h->upload_done);
+    hipFree(h->ws);
+    hipFree(h->inv_pool);
+    hipFree(h->status);
+    delete h;
+    return BT_OK;
+}
+
+const char* bt_si_sq_last_error(bt_si_sq_handle h) {
+    return h ? h->err.c_str() : g_last_error.c_str();
+}
+
+int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h) { return h ? h->last_launches : 0; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Diagnostic entry points (include/bt_si_sq_diag.h)
+// ---------------------------------------------------------------------------
+#include "../../include/bt_si_sq_diag.h"
+
+extern "C" {
+
+bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
+                             const double* alpha, const void* A, int32_t lda, int32_t opA,
+                             const void* B, int32_t ldb, int32_t opB,
+                             const double* beta, const void* C, int32_t ldc,
+                             void* D, int32_t ldd, int32_t mixed, void* hip_stream) {
+    if (m < 0 || n < 0 || k < 0 || !alpha || !beta || !D || (k > 0 && (!A || !B)))
+        return set_err(nullptr, BT_ERR_INVALID, "diag_gemm: bad arguments");
+    if (m == 0 || n == 0) return BT_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    GemmOp g;
+    memset(&g, 0, sizeof g);
+    g.D = reinterpret_cast<double2*>(D);
+    g.C = reinterpret_cast<const double2*>(C);
+    g.ldd = ldd;
+    g.ldc = ldc;
+    g.m = m;
+    g.n = n;
+    g.nterms = k > 0 ? 1 : 0;
+    g.tiles_n = gemm_tiles_n(n);
+    g.tile_begin = 0;
+    g.mixed = mixed;
+    g.beta = cplx(beta[0], beta[1]);
+    g.t[0].A = reinterpret_cast<const double2*>(A);
+    g.t[0].B = reinterpret_cast<const double2*>(B);
+    g.t[0].lda = lda;
+    g.t[0].ldb = ldb;
+    g.t[0].k = k;
+    g.t[0].flags = (opA ? kTermAH : 0) | (opB ? kTermBH : 0);
+    g.t[0].alpha = cplx(alpha[0], alpha[1]);
+    GemmOp* dop = nullptr;
+    hipError_t e = hipMalloc(&dop, sizeof g);
+    if (e != hipSuccess) return hip_err(nullptr, e, "hipMalloc");
+    e = hipMemcpyAsync(dop, &g, sizeof g, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_gemm(dop, 1, gemm_tiles(m, n), mixed != 0, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(dop);
+    if (e != hipSuccess) return hip_err(nullptr, e, "diag_gemm launch");
+    if (e2 != hipSuccess) return hip_err(nullptr, e2, "diag_gemm sync");
+    return BT_OK;
+}
+
+bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t count,
+                                int32_t* bad_index, void* hip_stream) {
+    if (bad_index) *bad_index = -1;
+    if (!src || !dst || d < 1 || d > kInvMaxDim || count < 0)
+        return set_err(nullptr, BT_ERR_INVALID, "diag_inverse: bad arguments (1 <= d <= 1024)");
+    if (count == 0) return BT_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    std::vector<OpRec> ops;
+    for (int i = 0; i < count; ++i) {
+        OpRec o;
+        o.kind = K_INV;
+        o.C = MatRef{const_cast<double2*>(reinterpret_cast<const double2*>(src)) + (size_t)i * d * d, d, d};
+        o.D = MatRef{reinterpret_cast<double2*>(dst) + (size_t)i * d * d, d, d};
+        o.tag = i;
+        ops.push_back(o);
+    }
+    int nl = levelize(ops);
+    Program dry = compile(ops, nl, reinterpret_cast<char*>((uintptr_t)1 << 40));
+    char* pool = nullptr;
+    char* dev = nullptr;
+    DevStatus* st = nullptr;
+    hipError_t e = hipMalloc(&pool, dry.inv_scratch_bytes);
+    if (e != hipSuccess) return set_err(nullptr, BT_ERR_OOM, "diag_inverse: scratch");
+    Program pg = compile(ops, nl, pool);
+    const size_t bg = pg.gemm.size() * sizeof(GemmOp), bi = pg.inv.size() * sizeof(InvJob);
+    const size_t off_inv = (bg + 255) & ~(size_t)255;
+    e = hipMalloc(&dev, off_inv + bi + 256);
+    if (e == hipSuccess) e = hipMalloc(&st, sizeof(DevStatus));
+    if (e != hipSuccess) { hipFree(pool); hipFree(dev); return set_err(nullptr, BT_ERR_OOM, "diag_inverse: op list"); }
+    std::vector<char> host(off_inv + bi + 256);
+    memcpy(host.data(), pg.gemm.data(), bg);
+    memcpy(host.data() + off_inv, pg.inv.data(), bi);
+    DevStatus z{0, 0};
+    e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st, &z, sizeof z, hipMemcpyHostToDevice);
+    GemmOp* dg = reinterpret_cast<GemmOp*>(dev);
+    InvJob* dj = reinterpret_cast<InvJob*>(dev + off_inv);
+    for (const Launch& L : pg.launches) {
+        if (e != hipSuccess) break;
+        switch (L.type) {
+            case 0: e = launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s); break;
+            case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
+            case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, st, s); break;
+            case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
+            default: break;
+        }
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    DevStatus out{0, 0};
+    if (e2 == hipSuccess) e2 = hipMemcpy(&out, st, sizeof out, hipMemcpyDeviceToHost);
+    hipFree(pool);
+    hipFree(dev);
+    hipFree(st);
+    if (e != hipSuccess) return hip_err(nullptr, e, "diag_inverse launch");
+    if (e2 != hipSuccess) return hip_err(nullptr, e2, "diag_inverse sync");
+    if (out.code != 0) {
+        if (bad_index) *bad_index = out.tag;
+        return set_err(nullptr, BT_ERR_SINGULAR, "diag_inverse: singular or non-finite pivot");
+    }
+    return BT_OK;
+}
+
+}  // extern "C"

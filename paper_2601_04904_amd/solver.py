@@ -1,0 +1,186 @@
+"""Thin Python binding over the C ABI: same names, argument marshalling only.
+
+PyTorch provides device memory and the HIP stream; every step of SI and SQ
+runs in the library's HIP kernels.  There is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import BT_FP64, BT_MIXED, BTError, check, make_desc
+
+FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a ROCm GPU is required (torch.cuda.is_available() is False)")
+    return torch
+
+
+class DeviceBlocks:
+    """Six complex128 device tensors in the layout of include/bt_si_sq.h."""
+
+    def __init__(self, diag, upper, lower, arrow_right, arrow_bottom, tip):
+        self.diag, self.upper, self.lower = diag, upper, lower
+        self.arrow_right, self.arrow_bottom, self.tip = arrow_right, arrow_bottom, tip
+
+    @property
+    def n(self):
+        return self.diag.shape[0]
+
+    @property
+    def b(self):
+        return self.diag.shape[1]
+
+    @property
+    def a(self):
+        return self.tip.shape[0]
+
+    @staticmethod
+    def empty(n: int, b: int, a: int, device="cuda", zero=False):
+        torch = _torch()
+        f = torch.zeros if zero else torch.empty
+        z = torch.complex128
+        m = max(n - 1, 0)
+        return DeviceBlocks(f((n, b, b), dtype=z, device=device), f((m, b, b), dtype=z, device=device),
+                            f((m, b, b), dtype=z, device=device), f((n, b, a), dtype=z, device=device),
+                            f((n, a, b), dtype=z, device=device), f((a, a), dtype=z, device=device))
+
+    @staticmethod
+    def from_host(M, device="cuda"):
+        torch = _torch()
+        t = [torch.from_numpy(np.ascontiguousarray(getattr(M, f), dtype=np.complex128)).to(device)
+             for f in FIELDS]
+        return DeviceBlocks(*t)
+
+    def to_host(self):
+        from types import SimpleNamespace
+        return SimpleNamespace(**{f: getattr(self, f).cpu().numpy() for f in FIELDS})
+
+    def c_blocks(self) -> _lib.bt_blocks:
+        bl = _lib.bt_blocks()
+        for f in FIELDS:
+            t = getattr(self, f)
+            assert t.is_contiguous() and t.dtype.is_complex
+            setattr(bl, f, t.data_ptr() if t.numel() > 0 else None)
+        return bl
+
+
+def workspace_bytes(n, b, a=0, partitions=1, bounds=None, precision=BT_FP64) -> int:
+    d = make_desc(n, b, a, partitions, bounds, precision)
+    return int(_lib.lib().bt_si_sq_workspace_bytes(C.byref(d)))
+
+
+def partition_bounds(n, b, a=0, partitions=1, bounds=None):
+    d = make_desc(n, b, a, partitions, bounds)
+    out = (C.c_int32 * (partitions + 1))()
+    check(_lib.lib().bt_si_sq_partition_bounds(C.byref(d), out))
+    return list(out)
+
+
+def flops(n, b, a=0, partitions=1, bounds=None):
+    """(executed, useful) real flops of one fused SI+SQ solve."""
+    d = make_desc(n, b, a, partitions, bounds)
+    ex, us = C.c_double(), C.c_double()
+    check(_lib.lib().bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)))
+    return ex.value, us.value
+
+
+class Solver:
+    """bt_si_sq_create / _factor / _selected_solve / _solve / _sync / _destroy."""
+
+    def __init__(self, n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, tol=1e-4,
+                 stream=None):
+        torch = _torch()
+        self.n, self.b, self.a = n, b, a
+        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        check(_lib.lib().bt_si_sq_create(C.byref(self._desc), C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def _blocks(self, M):
+        if M is None:
+            return None
+        bl = M.c_blocks()
+        self._keep.append(M)
+        return C.byref(bl)
+
+    def factor(self, A: DeviceBlocks, XR: DeviceBlocks = None):
+        self._keep = [A, XR]
+        check(_lib.lib().bt_si_sq_factor(self._h, self._blocks(A), self._blocks(XR)), self._h)
+
+    def selected_solve(self, B: DeviceBlocks, XL: DeviceBlocks):
+        err, fb = C.c_double(), C.c_int()
+        self._keep.extend([B, XL])
+        check(_lib.lib().bt_si_sq_selected_solve(self._h, self._blocks(B), self._blocks(XL),
+                                                 C.byref(err), C.byref(fb)), self._h)
+        return err.value, bool(fb.value)
+
+    def solve(self, A: DeviceBlocks, B: DeviceBlocks, XR: DeviceBlocks, XL: DeviceBlocks):
+        err, fb = C.c_double(), C.c_int()
+        self._keep = [A, B, XR, XL]
+        check(_lib.lib().bt_si_sq_solve(self._h, self._blocks(A), self._blocks(B), self._blocks(XR),
+                                        self._blocks(XL), C.byref(err), C.byref(fb)), self._h)
+        return err.value, bool(fb.value)
+
+    def sync(self):
+        check(_lib.lib().bt_si_sq_sync(self._h), self._h)
+
+    def last_launch_count(self) -> int:
+        return int(_lib.lib().bt_si_sq_last_launch_count(self._h))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _lib.lib().bt_si_sq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+__all__ = ["DeviceBlocks", "Solver", "workspace_bytes", "partition_bounds", "flops",
+           "BT_FP64", "BT_MIXED", "BTError"]
+
+
+def diag_gemm(alpha, A, opA, B, opB, beta=0.0, Cin=None, D=None, mixed=False, stream=None):
+    """D = beta Cin + alpha op(A) op(B) on the device (2-D complex128 tensors); returns D."""
+    torch = _torch()
+    m = A.shape[1] if opA else A.shape[0]
+    k = A.shape[0] if opA else A.shape[1]
+    n = B.shape[0] if opB else B.shape[1]
+    if D is None:
+        D = torch.empty((m, n), dtype=torch.complex128, device=A.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    al = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (C.c_double * 2)(complex(beta).real, complex(beta).imag)
+    check(_lib.lib().bt_si_sq_diag_gemm(
+        m, n, k, al, A.data_ptr(), A.stride(0), int(bool(opA)), B.data_ptr(), B.stride(0),
+        int(bool(opB)), be, Cin.data_ptr() if Cin is not None else None,
+        Cin.stride(0) if Cin is not None else 0, D.data_ptr(), D.stride(0), int(bool(mixed)),
+        C.c_void_p(st.cuda_stream)))
+    return D
+
+
+def diag_inverse(src, stream=None):
+    """Batched inverse of a (count, d, d) complex128 device tensor; returns (dst, bad_index)."""
+    torch = _torch()
+    src = src.contiguous()
+    dst = torch.empty_like(src)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    bad = C.c_int32(-1)
+    status = _lib.lib().bt_si_sq_diag_inverse(src.data_ptr(), dst.data_ptr(), src.shape[-1],
+                                              src.shape[0], C.byref(bad), C.c_void_p(st.cuda_stream))
+    if status not in (_lib.BT_OK, _lib.BT_ERR_SINGULAR):
+        check(status)
+    return dst, (bad.value if status == _lib.BT_ERR_SINGULAR else -1)

@@ -1,0 +1,136 @@
+"""C ABI on the CPU: the library loads, exports every declared symbol, and its
+host-only functions (descriptor validation, partition bounds, flop model,
+workspace size) behave.  No compute calls: there is no GPU here.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2601_04904_amd import _lib
+from paper_2601_04904_amd._lib import make_desc, BT_OK, BT_ERR_INVALID
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in ("bt_si_sq.h", "bt_si_sq_diag.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(bt_si_sq_[a-z_0-9]+)\s*\(", txt, re.M))
+    return names
+
+
+def test_header_parses():
+    names = declared_functions()
+    assert {"bt_si_sq_create", "bt_si_sq_factor", "bt_si_sq_selected_solve",
+            "bt_si_sq_destroy", "bt_si_sq_workspace_bytes"} <= names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(_lib.EXPORTED) == declared_functions()
+
+
+def test_struct_layout_matches_header():
+    # int32 n, b, a, partitions; pointer; int32 precision; double tol; uint32 flags
+    assert C.sizeof(_lib.bt_desc) == 48
+    assert C.sizeof(_lib.bt_blocks) == 6 * 8
+
+
+def _bounds(n, b, a, P, bounds=None):
+    d = make_desc(n, b, a, P, bounds)
+    out = (C.c_int32 * (P + 1))()
+    st = _lib.lib().bt_si_sq_partition_bounds(C.byref(d), out)
+    return st, list(out)
+
+
+def test_auto_bounds_balance():
+    st, bnd = _bounds(64, 512, 0, 8)
+    assert st == BT_OK
+    assert bnd == [0, 14, 20, 26, 32, 38, 44, 50, 64]
+    st, bnd = _bounds(128, 384, 512, 16)
+    assert st == BT_OK and bnd[0] == 0 and bnd[-1] == 128
+    sizes = [y - x for x, y in zip(bnd, bnd[1:])]
+    assert all(s >= 2 for s in sizes[1:-1]) and sizes[0] >= 1 and sizes[-1] >= 1
+
+
+@pytest.mark.parametrize("n,b,a,P,bounds", [
+    (0, 4, 0, 1, None), (4, 0, 0, 1, None), (4, 4, -1, 1, None), (4, 4, 0, 0, None),
+    (6, 4, 0, 3, [0, 2, 3, 6]),      # middle partition of one block
+    (6, 4, 0, 2, [0, 3, 5]),         # does not end at n
+    (6, 4, 0, 2, [1, 3, 6]),         # does not start at 0
+    (4, 2000, 0, 1, None),           # block size above the supported maximum
+])
+def test_invalid_descriptors(n, b, a, P, bounds):
+    d = make_desc(n, b, a, P, bounds)
+    assert _lib.lib().bt_si_sq_workspace_bytes(C.byref(d)) == 0
+    out = (C.c_int32 * (max(P, 1) + 1))()
+    assert _lib.lib().bt_si_sq_partition_bounds(C.byref(d), out) == BT_ERR_INVALID
+    h = C.c_void_p()
+    assert _lib.lib().bt_si_sq_create(C.byref(d), None, C.byref(h)) == BT_ERR_INVALID
+    assert h.value is None
+    assert len(_lib.lib().bt_si_sq_last_error(None)) > 0
+
+
+def _flops(n, b, a, P, bounds=None):
+    d = make_desc(n, b, a, P, bounds)
+    ex, us = C.c_double(), C.c_double()
+    assert _lib.lib().bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)) == BT_OK
+    return ex.value, us.value
+
+
+@pytest.mark.parametrize("n,b,a", [(1, 8, 0), (2, 8, 0), (16, 32, 0), (64, 512, 0), (5, 7, 3),
+                                   (128, 384, 512)])
+def test_flop_model_sequential(n, b, a):
+    """Sequential SI+SQ op list: per eliminated block with D = sum of its neighbour sizes,
+    inverse 8b^3 + products 8(2b^3 + 11Db^2 + 10D^2 b) (counted independently here)."""
+    ex, us = _flops(n, b, a, 1)
+    assert ex == us
+
+    def step(dk, Ns):
+        D = sum(Ns)
+        f = 8 * dk ** 3                              # inverse
+        f += 8 * dk * dk * D                         # T_u
+        f += 8 * D * D * dk                          # A updates
+        f += 16 * dk ** 3                            # S_B
+        f += 8 * dk * dk * D                         # W_u
+        f += 3 * 8 * D * D * dk                      # B updates
+        f += 8 * dk * dk * D + 8 * D * D * dk        # tau, rho
+        f += 8 * D * dk * dk + 8 * dk * D * D        # X_uk, X_kv
+        f += 8 * D * dk * dk                         # X_kk
+        f += 8 * D * D * dk * 2                      # GB, BG
+        f += 2 * 8 * D * dk * dk                     # Y21
+        f += 2 * 8 * dk * dk * D + 8 * dk * D * D    # L_kv (Y12 + update)
+        f += 8 * D * D * dk                          # L_uk
+        f += 2 * 8 * dk * dk * D                     # L_kk
+        return f
+
+    ref = 0
+    for k in range(n):
+        Ns = ([b] if k + 1 < n else []) + ([a] if a else [])
+        ref += step(b, Ns)
+    if a:
+        ref += step(a, [])
+    assert ex == pytest.approx(ref, rel=1e-12)
+    if a == 0:
+        assert ex == pytest.approx(192 * (n - 1) * b ** 3 + 24 * b ** 3, rel=1e-12)
+
+
+def test_flop_model_partitioned_executes_more():
+    ex, us = _flops(64, 512, 0, 8)
+    assert us == pytest.approx(192 * 63 * 512 ** 3 + 24 * 512 ** 3)
+    assert 1.5 < ex / us < 1.8
+
+
+def test_workspace_bytes_scales():
+    d1 = make_desc(16, 32, 0, 1)
+    d2 = make_desc(64, 512, 0, 1)
+    w1 = _lib.lib().bt_si_sq_workspace_bytes(C.byref(d1))
+    w2 = _lib.lib().bt_si_sq_workspace_bytes(C.byref(d2))
+    assert 0 < w1 < w2
+    # dominated by O(n b^2) block storage
+    assert w2 < 40 * 64 * 512 * 512 * 16

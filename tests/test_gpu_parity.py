@@ -1,0 +1,179 @@
+"""End-to-end parity of the HIP path against the CPU oracle, through the C ABI.
+
+FP64 bar: max relative Frobenius error per selected block <= 1e-11
+(rel_err in tests/_util.py).  Sizes span several 64 x 32 product tiles,
+several 16-column inverse panels and ragged tails; partitioned runs use
+explicit and cost-model bounds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_04904_amd.synth import gen_problem, equilibrium_B
+from tests._util import rel_err, even_bounds
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2601_04904_amd import solver
+    return solver
+
+
+def run_solver(S, A, B, partitions=1, bounds=None, fused=True, with_xr=True):
+    n, b, a = A.diag.shape[0], A.diag.shape[1], A.tip.shape[0]
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR = S.DeviceBlocks.empty(n, b, a) if with_xr else None
+    XL = S.DeviceBlocks.empty(n, b, a)
+    sol = S.Solver(n, b, a, partitions=partitions, bounds=bounds)
+    if fused:
+        sol.solve(dA, dB, XR, XL)
+    else:
+        sol.factor(dA, XR)
+        sol.selected_solve(dB, XL)
+    sol.sync()
+    out = (XR.to_host() if with_xr else None), XL.to_host()
+    sol.destroy()
+    return out
+
+
+CASES = [
+    # n, b, a, partitions, bounds
+    (1, 5, 0, 1, None),
+    (2, 3, 0, 1, None),
+    (16, 32, 0, 1, None),
+    (16, 32, 0, 2, None),
+    (16, 32, 0, 4, None),
+    (9, 37, 0, 3, [0, 3, 6, 9]),
+    (7, 40, 19, 1, None),
+    (12, 24, 20, 3, None),
+    (10, 33, 65, 4, [0, 2, 4, 6, 10]),
+    (6, 70, 17, 2, [0, 1, 6]),
+]
+
+
+@pytest.mark.parametrize("n,b,a,P,bounds", CASES)
+def test_parity_small(S, n, b, a, P, bounds):
+    print(f"case n={n} b={b} a={a} P={P} bounds={bounds}", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-3, seed=n + b + a + P)
+    R0, L0 = oracle.solve_dense(A, B)
+    XR, XL = run_solver(S, A, B, P, bounds)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    print(f"  err R={eR:.3e} L={eL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL
+
+
+def test_factor_then_selected_solve_matches_fused(S):
+    A, B = gen_problem(10, 48, 16, seed=3)
+    R0, L0 = oracle.solve_dense(A, B)
+    XR, XL = run_solver(S, A, B, 2, None, fused=False)
+    assert rel_err(XR, R0) < TOL and rel_err(XL, L0) < TOL
+
+
+def test_without_xr_output(S):
+    A, B = gen_problem(8, 40, 0, seed=4)
+    _, L0 = oracle.solve_dense(A, B)
+    _, XL = run_solver(S, A, B, 1, None, with_xr=False)
+    assert rel_err(XL, L0) < TOL
+
+
+def test_two_right_hand_sides_share_factors(S):
+    """G^< and G^> style: one factor, two selected solves."""
+    import torch
+    n, b, a = 9, 32, 12
+    A, B1 = gen_problem(n, b, a, seed=11)
+    from paper_2601_04904_amd.synth import gen_B
+    B2 = gen_B(np.random.Generator(np.random.PCG64(12)), n, b, a)
+    dA = S.DeviceBlocks.from_host(A)
+    XR, XL1, XL2 = (S.DeviceBlocks.empty(n, b, a) for _ in range(3))
+    sol = S.Solver(n, b, a, partitions=2)
+    sol.factor(dA, XR)
+    sol.selected_solve(S.DeviceBlocks.from_host(B1), XL1)
+    sol.selected_solve(S.DeviceBlocks.from_host(B2), XL2)
+    sol.sync()
+    R0, L1 = oracle.solve_dense(A, B1)
+    _, L2 = oracle.solve_dense(A, B2)
+    assert rel_err(XR.to_host(), R0) < TOL
+    assert rel_err(XL1.to_host(), L1) < TOL
+    assert rel_err(XL2.to_host(), L2) < TOL
+    sol.destroy()
+    torch.cuda.synchronize()
+
+
+def test_repeat_calls_identical(S):
+    """Same handle, same inputs: bitwise identical results (no races)."""
+    n, b, a = 12, 64, 32
+    A, B = gen_problem(n, b, a, seed=21)
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    sol = S.Solver(n, b, a, partitions=3)
+    outs = []
+    for _ in range(3):
+        XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+        sol.solve(dA, dB, XR, XL)
+        sol.sync()
+        outs.append((XR.to_host(), XL.to_host()))
+    for o in outs[1:]:
+        for f in ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip"):
+            assert np.array_equal(getattr(o[0], f), getattr(outs[0][0], f))
+            assert np.array_equal(getattr(o[1], f), getattr(outs[0][1], f))
+    sol.destroy()
+
+
+def test_singular_block_reported(S):
+    from paper_2601_04904_amd._lib import BTError, BT_ERR_SINGULAR
+    n, b = 4, 16
+    A, B = gen_problem(n, b, 0, seed=1)
+    A.diag[0][:, 3] = 0.0
+    A.upper[0][:, :] = 0.0      # keep block 0 decoupled so its Schur block stays singular
+    A.lower[0][:, :] = 0.0
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, 0), S.DeviceBlocks.empty(n, b, 0)
+    sol = S.Solver(n, b, 0)
+    sol.solve(dA, dB, XR, XL)
+    with pytest.raises(BTError) as ei:
+        sol.sync()
+    assert ei.value.status == BT_ERR_SINGULAR
+    assert "block 0" in str(ei.value)
+    sol.sync()   # the flag is cleared after being reported
+    sol.destroy()
+
+
+def test_state_and_argument_errors(S):
+    from paper_2601_04904_amd._lib import BTError, BT_ERR_STATE, BT_ERR_INVALID
+    sol = S.Solver(4, 8, 0)
+    XL = S.DeviceBlocks.empty(4, 8, 0)
+    A, B = gen_problem(4, 8, 0, seed=0)
+    with pytest.raises(BTError) as ei:
+        sol.selected_solve(S.DeviceBlocks.from_host(B), XL)
+    assert ei.value.status == BT_ERR_STATE
+    sol.destroy()
+    sol = S.Solver(4, 8, 3)
+    A, B = gen_problem(4, 8, 0, seed=0)   # no arrow blocks for an a = 3 handle
+    with pytest.raises(BTError) as ei:
+        sol.solve(S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B), None, XL)
+    assert ei.value.status == BT_ERR_INVALID
+    sol.destroy()
+
+
+def test_fluctuation_dissipation_on_gpu(S):
+    """B = c(A^H - A) gives X^< = c(X^R - X^R^H) blockwise, a check of SQ against SI."""
+    n, b, a = 20, 64, 40
+    A, _ = gen_problem(n, b, a, eta=1e-2, seed=8)
+    c = 0.5
+    B = equilibrium_B(A, c)
+    XR, XL = run_solver(S, A, B, 4, None)
+    worst = 0.0
+    for i in range(n):
+        ref = c * (XR.diag[i] - XR.diag[i].conj().T)
+        worst = max(worst, np.linalg.norm(XL.diag[i] - ref) / np.linalg.norm(ref))
+    for i in range(n - 1):
+        ref = c * (XR.upper[i] - XR.lower[i].conj().T)
+        worst = max(worst, np.linalg.norm(XL.upper[i] - ref) / np.linalg.norm(ref))
+    ref = c * (XR.tip - XR.tip.conj().T)
+    worst = max(worst, np.linalg.norm(XL.tip - ref) / np.linalg.norm(ref))
+    assert worst < TOL
