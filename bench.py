@@ -1,0 +1,230 @@
+#!/usr/bin/env python
+"""Benchmark: fused selected inversion + selected quadratic solve (SI+SQ) on one MI355X.
+
+One step = one fused SI+SQ solve (factor of A, forward B-chain, backward SI and
+SQ sweeps) of the workload, with A and B already resident in HBM.  Prints one
+JSON line.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload bt_n64_b512]
+                    [--partitions P] [--compare-partitions Q] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 MFMA
+FP32_PEAK_TFLOPS = 157.3    # MI355X dense FP32 MFMA
+HBM_PEAK_GBS = 8000.0
+METRIC = "SI+SQ solves/s, % FP64/FP32 MFMA peak, p50/p99 latency vs plain RGF"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def time_solves(torch, sol, dA, dB, XR, XL, steps, warmup):
+    for _ in range(warmup):
+        sol.solve(dA, dB, XR, XL)
+    sol.sync()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(steps):
+        sol.solve(dA, dB, XR, XL)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol.sync()
+    lat = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return t1 - t0, lat
+
+
+def cpu_baseline(A, B, seconds, XR_gpu, XL_gpu):
+    """The oracle (sequential RGF, NumPy complex128) on the host cores, bounded sample."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 0) for p in threadpool_info()] or [0])
+    except Exception:
+        threads = 0
+    cores = threads or len(os.sched_getaffinity(0))
+    n_done, t_total, res = 0, 0.0, None
+    while t_total < seconds and n_done < 5:
+        t0 = time.perf_counter()
+        res = oracle.rgf_bta(A, B) if A.tip.shape[0] else oracle.rgf_bt(A, B)
+        t_total += time.perf_counter() - t0
+        n_done += 1
+        if t_total / n_done * (n_done + 1) > 2.0 * seconds:
+            break
+    # parity of the timed GPU result against this oracle run (same inputs)
+    def rel(X, R):
+        worst = 0.0
+        fields = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
+        big = 0.0
+        for f in fields:
+            r = np.asarray(getattr(R, f))
+            if r.size:
+                big = max(big, max(np.linalg.norm(x) for x in r.reshape(-1, *r.shape[-2:])))
+        for f in fields:
+            r = np.asarray(getattr(R, f))
+            if r.size == 0:
+                continue
+            x = np.asarray(getattr(X, f))
+            if r.ndim == 2:
+                r, x = r[None], x[None]
+            for i in range(r.shape[0]):
+                den = max(np.linalg.norm(r[i]), 1e-6 * big)
+                worst = max(worst, float(np.linalg.norm(x[i] - r[i]) / den))
+        return worst
+    errR = rel(XR_gpu, res[0])
+    errL = rel(XL_gpu, res[1])
+    return dict(value=n_done / t_total, unit="solves/s", cores=cores, kind="oracle",
+                sample=f"{n_done} full sequential RGF solve(s) of the same workload "
+                       f"(NumPy complex128, {t_total:.1f} s)"), (errR, errL)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bt_n64_b512")
+    ap.add_argument("--partitions", type=int, default=None,
+                    help="partitions of the timed solve (default: the workload's first entry)")
+    ap.add_argument("--compare-partitions", type=int, default=None,
+                    help="also time this partition count and report it beside the headline")
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the partitioned "
+              "solve runs its partitions concurrently on one device and does not shard across "
+              "GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2601_04904_amd import solver as S
+    from paper_2601_04904_amd.synth import CONFIGS, gen_problem
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    cfg = CONFIGS[args.workload]
+    P = args.partitions if args.partitions is not None else cfg.partitions[0]
+    n, b, a = cfg.n, cfg.b, cfg.a
+    log(f"[bench] workload {cfg.name}: n={n} b={b} a={a} P={P} eta={cfg.eta}")
+    t0 = time.perf_counter()
+    A, B = gen_problem(n, b, a, cfg.E, cfg.eta, cfg.seed)
+    log(f"[bench] generated inputs in {time.perf_counter() - t0:.1f} s")
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+
+    sol = S.Solver(n, b, a, partitions=P)
+    elapsed, lat = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
+    launches = sol.last_launch_count()
+    ms = 1e3 * elapsed / args.steps
+    ex, us = S.flops(n, b, a, P)
+    log(f"[bench] P={P}: {ms:.2f} ms/solve, {launches} launches/solve")
+
+    # roofline of the dominant kernel, from HIP events around each launch
+    sol.profile(True)
+    for _ in range(args.profile_steps):
+        sol.solve(dA, dB, XR, XL)
+    stats = sol.profile_stats()
+    sol.profile(False)
+    sol.sync()
+    dom_name = max(stats, key=lambda k: stats[k]["total_ms"])
+    dom = stats[dom_name]
+    per_launch_ms = dom["total_ms"] / dom["launches"]
+    if dom_name.startswith("product"):
+        peak = FP64_PEAK_TFLOPS if dom_name == "product_fp64" else FP32_PEAK_TFLOPS
+        achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(achieved / peak, 4), traffic=None)
+    else:
+        achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    roof["kernel"] = dom_name
+    roof["launches_per_solve"] = dom["launches"] / args.profile_steps
+    roof["avg_launch_us"] = round(per_launch_ms * 1e3, 2)
+    kernel_share = {k: round(v["total_ms"] / args.profile_steps, 3) for k, v in stats.items()}
+    log(f"[bench] per-solve kernel ms: {kernel_share}")
+
+    compare = None
+    if args.compare_partitions is not None and args.compare_partitions != P:
+        Q = args.compare_partitions
+        solq = S.Solver(n, b, a, partitions=Q)
+        XR2, XL2 = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+        el2, lat2 = time_solves(torch, solq, dA, dB, XR2, XL2, args.steps, args.warmup)
+        ex2, _ = S.flops(n, b, a, Q)
+        compare = dict(partitions=Q, solves_per_s=round(args.steps / el2, 4),
+                       ms_per_step=round(1e3 * el2 / args.steps, 3),
+                       pct_fp64_peak_executed=round(100 * ex2 / (el2 / args.steps) / 1e12 / FP64_PEAK_TFLOPS, 2),
+                       pct_fp64_peak_useful=round(100 * us / (el2 / args.steps) / 1e12 / FP64_PEAK_TFLOPS, 2))
+        log(f"[bench] P={Q}: {compare['ms_per_step']:.2f} ms/solve")
+        solq.destroy()
+        del XR2, XL2
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        XRh, XLh = XR.to_host(), XL.to_host()
+        cpu, (eR, eL) = cpu_baseline(A, B, args.cpu_seconds, XRh, XLh)
+        cpu["gpu_max_rel_err_vs_oracle"] = {"XR": eR, "XL": eL}
+        log(f"[bench] cpu {cpu['value']:.4f} solves/s on {cpu['cores']} threads; "
+            f"GPU error vs oracle R={eR:.2e} L={eL:.2e}")
+
+    tflops_ex = ex / (elapsed / args.steps) / 1e12
+    tflops_us = us / (elapsed / args.steps) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n": n, "b": b, "a": a, "partitions": P,
+                   "E": cfg.E, "eta": cfg.eta, "seed": cfg.seed},
+        "tflops_executed": round(tflops_ex, 3),
+        "tflops_useful": round(tflops_us, 3),
+        "pct_fp64_peak_executed": round(100 * tflops_ex / FP64_PEAK_TFLOPS, 2),
+        "pct_fp64_peak_useful": round(100 * tflops_us / FP64_PEAK_TFLOPS, 2),
+        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
+        "launches_per_solve": launches,
+        "kernel_ms_per_solve": kernel_share,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if compare:
+        out["compare"] = compare
+    print(json.dumps(out), flush=True)
+    sol.destroy()
+
+
+if __name__ == "__main__":
+    main()

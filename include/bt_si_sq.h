@@ -29,12 +29,14 @@
  * complex numbers).
  *
  * Ownership.  The caller owns A, B and the output blocks (device memory it
- * allocated).  The library never writes to A or B.  The handle owns its
- * workspace (device memory allocated at create, freed at destroy), which
- * holds the stored factors; X^R written by bt_si_sq_factor and the factors
- * stay valid until the next factor call or destroy, so selected_solve may be
- * called any number of times (different B, e.g. Sigma^< and Sigma^>) after
- * one factor.
+ * allocated).  The library never writes to A or B, and outputs must not
+ * alias inputs.  The handle owns its workspace (device memory allocated at
+ * create, freed at destroy), which holds the stored factors and the updated
+ * (Schur-complemented) blocks.  After bt_si_sq_factor, selected_solve may be
+ * called any number of times (different B, e.g. Sigma^< and Sigma^>); it
+ * reads the original off-diagonal and arrow blocks of A and the X^R blocks
+ * where factor left them, so A and the XR given to factor (if any) must stay
+ * allocated and unmodified until the last selected_solve.
  *
  * Streams and errors.  Calls that take a handle enqueue work on the HIP
  * stream given at create and return without waiting, except that they may
@@ -160,6 +162,38 @@ const char* bt_si_sq_last_error(bt_si_sq_handle h);
 
 /* Number of kernel launches of the last enqueued solve (diagnostics). */
 int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h);
+
+/* Per-kernel measurement.  With enable != 0 every launch of the following
+ * factor/selected_solve/solve calls is bracketed by HIP events recorded on
+ * the handle's stream, and bt_si_sq_profile_stats returns, per kernel
+ * family, the launch count, the summed event time and the summed
+ * algorithmic work of those launches.  Enabling (or disabling) clears the
+ * totals.  Event bracketing adds host work per launch; time whole solves
+ * with profiling off. */
+typedef enum {
+    BT_KERNEL_PRODUCT_FP64 = 0,   /* grouped complex products, FP64 MFMA */
+    BT_KERNEL_PRODUCT_MIXED = 1,  /* grouped complex products, FP32 MFMA */
+    BT_KERNEL_INV_PANEL = 2,      /* inverse: panel elimination */
+    BT_KERNEL_INV_INIT = 3,       /* inverse: working copy */
+    BT_KERNEL_INV_FINISH = 4,     /* inverse: unscramble into the result */
+    BT_KERNEL_SUM = 5,            /* elementwise block sums */
+    BT_KERNEL_COUNT = 6
+} bt_kernel_kind;
+
+typedef struct {
+    int32_t kind;        /* bt_kernel_kind */
+    int32_t launches;
+    double total_ms;     /* summed HIP-event time of the launches */
+    double flops;        /* summed algorithmic real flops (complex m x n x k product = 8mnk) */
+    double bytes;        /* summed algorithmic HBM bytes (each operand read once, result written once) */
+} bt_kernel_stat;
+
+bt_status bt_si_sq_profile(bt_si_sq_handle h, int32_t enable);
+
+/* Waits for the stream, then writes up to max_entries stats (one per kernel
+ * family that ran) into out and their number into *count. */
+bt_status bt_si_sq_profile_stats(bt_si_sq_handle h, bt_kernel_stat* out, int32_t max_entries,
+                                 int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -32,6 +32,12 @@ bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
 bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t count,
                                 int32_t* bad_index, void* hip_stream);
 
+/* Schedule of a fused solve for this descriptor, as text: one line per
+ * dependency level with its number of products, product tiles (64 x 32
+ * complex) and inverses.  Pure host computation.  Writes at most cap bytes
+ * (NUL-terminated) and returns the length the full text needs. */
+size_t bt_si_sq_diag_schedule(const bt_desc* desc, char* out, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

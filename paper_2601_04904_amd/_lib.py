@@ -16,8 +16,12 @@ EXPORTED = [
     "bt_si_sq_workspace_bytes", "bt_si_sq_partition_bounds", "bt_si_sq_flops",
     "bt_si_sq_create", "bt_si_sq_factor", "bt_si_sq_selected_solve", "bt_si_sq_solve",
     "bt_si_sq_sync", "bt_si_sq_destroy", "bt_si_sq_last_error", "bt_si_sq_last_launch_count",
-    "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse",
+    "bt_si_sq_profile", "bt_si_sq_profile_stats",
+    "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse", "bt_si_sq_diag_schedule",
 ]
+
+KERNEL_NAMES = {0: "product_fp64", 1: "product_mixed", 2: "inv_panel", 3: "inv_init",
+                4: "inv_finish", 5: "sum"}
 
 
 class bt_desc(C.Structure):
@@ -29,6 +33,11 @@ class bt_desc(C.Structure):
 class bt_blocks(C.Structure):
     _fields_ = [("diag", C.c_void_p), ("upper", C.c_void_p), ("lower", C.c_void_p),
                 ("arrow_right", C.c_void_p), ("arrow_bottom", C.c_void_p), ("tip", C.c_void_p)]
+
+
+class bt_kernel_stat(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("launches", C.c_int32), ("total_ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 class BTError(RuntimeError):
@@ -74,6 +83,11 @@ def lib():
     L.bt_si_sq_last_error.restype = C.c_char_p
     L.bt_si_sq_last_launch_count.argtypes = [H]
     L.bt_si_sq_last_launch_count.restype = C.c_int32
+    L.bt_si_sq_profile.argtypes = [H, C.c_int32]
+    L.bt_si_sq_profile.restype = C.c_int
+    L.bt_si_sq_profile_stats.argtypes = [H, C.POINTER(bt_kernel_stat), C.c_int32,
+                                         C.POINTER(C.c_int32)]
+    L.bt_si_sq_profile_stats.restype = C.c_int
     dp = C.POINTER(C.c_double)
     L.bt_si_sq_diag_gemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_void_p, C.c_int32,
                                      C.c_int32, C.c_void_p, C.c_int32, C.c_int32, dp, C.c_void_p,
@@ -82,6 +96,8 @@ def lib():
     L.bt_si_sq_diag_inverse.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_int32), C.c_void_p]
     L.bt_si_sq_diag_inverse.restype = C.c_int
+    L.bt_si_sq_diag_schedule.argtypes = [C.POINTER(bt_desc), C.c_char_p, C.c_size_t]
+    L.bt_si_sq_diag_schedule.restype = C.c_size_t
     _lib = L
     return L
 

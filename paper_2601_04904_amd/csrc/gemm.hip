@@ -68,76 +68,139 @@ __device__ inline int find_op(const GemmOp* __restrict__ ops, int nops, int bid)
     return lo;
 }
 
-// Global -> registers for one stage of term T at k offset k0.
-__device__ inline void load_stage(const GemmTerm& T, int m, int n, int i0, int j0, int k0,
-                                  int tid, double2 ra[4], double2 rb[2]) {
+// Global -> registers for one stage of term T at k offset k0.  Loads are
+// unconditional (indices clamped into the matrix, out-of-range values replaced
+// by zero afterwards) so that all of a stage's loads are in flight together.
+#ifdef __HIP_DEVICE_COMPILE__
+typedef const __attribute__((address_space(1))) double2* gptr_t;
+#else
+typedef const double2* gptr_t;
+#endif
+
+// Raw operands of one stage in flight: values, in-range flags and the term's
+// op / alpha needed to finish them.
+template <int BM>
+struct Stage {
+    double2 ra[BM * kBK / kThreads];
+    double2 rb[kBN * kBK / kThreads];
+    bool oka[BM * kBK / kThreads];
+    bool okb[kBN * kBK / kThreads];
+    bool ah, bh;
+    double2 alpha;
+};
+
+// Issue the global loads of one stage of term T at k offset k0.  Loads are
+// unconditional (indices clamped into the matrix; out-of-range values are
+// replaced by zero in finish_stage) so that they are all in flight together
+// and overlap the MFMAs of the current stage.
+template <int BM>
+__device__ inline void issue_stage(const GemmTerm& T, int m, int n, int i0, int j0, int k0,
+                                   int tid, Stage<BM>& st) {
+    constexpr int NA = BM * kBK / kThreads;
+    constexpr int NB = kBN * kBK / kThreads;
     const bool ah = T.flags & kTermAH;
     const bool bh = T.flags & kTermBH;
+    st.ah = ah;
+    st.bh = bh;
+    st.alpha = T.alpha;
+    const int km1 = T.k - 1;
+    const gptr_t Ap = (gptr_t)T.A;
+    const gptr_t Bp = (gptr_t)T.B;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NA; ++q) {
         const int e = tid + kThreads * q;
-        const int i = ah ? (e & 63) : (e >> 4);
-        const int p = ah ? (e >> 6) : (e & 15);
+        const int i = ah ? (e % BM) : (e / kBK);
+        const int p = ah ? (e / BM) : (e % kBK);
         const int gi = i0 + i, gp = k0 + p;
-        double2 v = make_double2(0.0, 0.0);
-        if (gi < m && gp < T.k) {
-            if (ah) { v = T.A[(size_t)gp * T.lda + gi]; v.y = -v.y; }
-            else    { v = T.A[(size_t)gi * T.lda + gp]; }
-        }
-        ra[q] = v;
+        st.oka[q] = gi < m && gp <= km1;
+        const int gic = min(gi, m - 1), gpc = min(gp, km1);
+        const size_t idx = ah ? (size_t)gpc * T.lda + gic : (size_t)gic * T.lda + gpc;
+        st.ra[q] = Ap[idx];
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NB; ++q) {
         const int e = tid + kThreads * q;
-        const int j = bh ? (e >> 4) : (e & 31);
-        const int p = bh ? (e & 15) : (e >> 5);
+        const int j = bh ? (e / kBK) : (e % kBN);
+        const int p = bh ? (e % kBK) : (e / kBN);
         const int gj = j0 + j, gp = k0 + p;
-        double2 v = make_double2(0.0, 0.0);
-        if (gj < n && gp < T.k) {
-            if (bh) { v = T.B[(size_t)gj * T.ldb + gp]; v.y = -v.y; }
-            else    { v = T.B[(size_t)gp * T.ldb + gj]; }
-        }
-        rb[q] = cmul(T.alpha, v);
+        st.okb[q] = gj < n && gp <= km1;
+        const int gjc = min(gj, n - 1), gpc = min(gp, km1);
+        const size_t idx = bh ? (size_t)gjc * T.ldb + gpc : (size_t)gpc * T.ldb + gjc;
+        st.rb[q] = Bp[idx];
     }
 }
 
-template <bool MIXED>
-__device__ inline void store_stage(bool ah, bool bh, int tid, const double2 ra[4], const double2 rb[2],
-                                   typename Prec<MIXED>::C (*As)[kBM + 1],
+// Conjugate, scale by alpha and zero the out-of-range values.  The empty asm
+// consumes every loaded value, so the compiler cannot turn the loads back
+// into conditional ones.
+template <int BM>
+__device__ inline void finish_stage(Stage<BM>& st) {
+    constexpr int NA = BM * kBK / kThreads;
+    constexpr int NB = kBN * kBK / kThreads;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) asm volatile("" : "+v"(st.ra[q].x), "+v"(st.ra[q].y));
+#pragma unroll
+    for (int q = 0; q < NB; ++q) asm volatile("" : "+v"(st.rb[q].x), "+v"(st.rb[q].y));
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        double2 v = st.ra[q];
+        v.y = st.ah ? -v.y : v.y;
+        st.ra[q] = st.oka[q] ? v : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        double2 v = st.rb[q];
+        v.y = st.bh ? -v.y : v.y;
+        v = cmul(st.alpha, v);
+        st.rb[q] = st.okb[q] ? v : make_double2(0.0, 0.0);
+    }
+}
+
+template <bool MIXED, int BM>
+__device__ inline void store_stage(int tid, const Stage<BM>& st,
+                                   typename Prec<MIXED>::C (*As)[BM + 1],
                                    typename Prec<MIXED>::C (*Bs)[kBN + 1]) {
+    constexpr int NA = BM * kBK / kThreads;
+    constexpr int NB = kBN * kBK / kThreads;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NA; ++q) {
         const int e = tid + kThreads * q;
-        const int i = ah ? (e & 63) : (e >> 4);
-        const int p = ah ? (e >> 6) : (e & 15);
-        As[p][i] = Prec<MIXED>::cvt(ra[q]);
+        const int i = st.ah ? (e % BM) : (e / kBK);
+        const int p = st.ah ? (e / BM) : (e % kBK);
+        As[p][i] = Prec<MIXED>::cvt(st.ra[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NB; ++q) {
         const int e = tid + kThreads * q;
-        const int j = bh ? (e >> 4) : (e & 31);
-        const int p = bh ? (e & 15) : (e >> 5);
-        Bs[p][j] = Prec<MIXED>::cvt(rb[q]);
+        const int j = st.bh ? (e / kBK) : (e % kBN);
+        const int p = st.bh ? (e % kBK) : (e / kBN);
+        Bs[p][j] = Prec<MIXED>::cvt(st.rb[q]);
     }
 }
 
-template <bool MIXED>
+// One workgroup computes a BM x kBN complex tile; its 4 waves split the tile
+// 2 x 2 (BM/2 rows x 32 real columns each, i.e. MI x 2 MFMA blocks).
+template <bool MIXED, int BM>
 __global__ __launch_bounds__(kThreads)
 void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     typedef typename Prec<MIXED>::C CT;
     typedef typename Prec<MIXED>::R RT;
     typedef typename Prec<MIXED>::Acc AccT;
-    __shared__ CT As[2][kBK][kBM + 1];
+    constexpr int MI = BM / 32;
+    __shared__ CT As[2][kBK][BM + 1];
     __shared__ CT Bs[2][kBK][kBN + 1];
+    __shared__ GemmTerm terms[kMaxTerms];
 
     const int bid = blockIdx.x;
     const GemmOp* op = ops + find_op(ops, nops, bid);
     const int m = op->m, n = op->n, nterms = op->nterms;
     const int local = bid - op->tile_begin;
     const int tm = local / op->tiles_n, tn = local - tm * op->tiles_n;
-    const int i0 = tm * kBM, j0 = tn * kBN;
-
+    const int i0 = tm * BM, j0 = tn * kBN;
     const int tid = threadIdx.x;
+    if (tid < nterms) terms[tid] = op->t[tid];
+    __syncthreads();
+
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int cA = (lane >> 4) & 1;   // real k within the pair: 0 = re part of A, 1 = im part
@@ -145,35 +208,36 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     const int r16 = lane & 15;
     const int d = lane & 1;           // output component of this lane's B'' column
 
-    AccT acc[2][2];
+    AccT acc[MI][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MI; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
             acc[a][b] = AccT{0, 0, 0, 0};
 
     int t = 0, k0 = 0;
-    while (t < nterms && op->t[t].k <= 0) ++t;
-    double2 ra[4], rb[2];
+    while (t < nterms && terms[t].k <= 0) ++t;
+    Stage<BM> st;
     int buf = 0;
     if (t < nterms) {
-        load_stage(op->t[t], m, n, i0, j0, k0, tid, ra, rb);
-        store_stage<MIXED>(op->t[t].flags & kTermAH, op->t[t].flags & kTermBH, tid, ra, rb, As[0], Bs[0]);
+        issue_stage<BM>(terms[t], m, n, i0, j0, k0, tid, st);
+        finish_stage<BM>(st);
+        store_stage<MIXED, BM>(tid, st, As[0], Bs[0]);
     }
     __syncthreads();
     while (t < nterms) {
         int tn2 = t, kn = k0 + kBK;
-        while (tn2 < nterms && kn >= op->t[tn2].k) { ++tn2; kn = 0; }
+        while (tn2 < nterms && kn >= terms[tn2].k) { ++tn2; kn = 0; }
         const bool has_next = tn2 < nterms;
-        if (has_next) load_stage(op->t[tn2], m, n, i0, j0, kn, tid, ra, rb);
+        if (has_next) issue_stage<BM>(terms[tn2], m, n, i0, j0, kn, tid, st);
 
 #pragma unroll
         for (int kk = 0; kk < kBK / 2; ++kk) {
             const int p = 2 * kk + pOff;
-            RT av[2], bv[2];
+            RT av[MI], bv[2];
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi) {
-                const CT x = As[buf][p][wm * 32 + mi * 16 + r16];
+            for (int mi = 0; mi < MI; ++mi) {
+                const CT x = As[buf][p][wm * (BM / 2) + mi * 16 + r16];
                 av[mi] = cA ? x.y : x.x;
             }
 #pragma unroll
@@ -184,46 +248,78 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
                 bv[ni] = (cA == 1 && d == 0) ? -v : v;
             }
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < 2; ++ni)
                     acc[mi][ni] = Prec<MIXED>::mfma(av[mi], bv[ni], acc[mi][ni]);
         }
-        if (has_next)
-            store_stage<MIXED>(op->t[tn2].flags & kTermAH, op->t[tn2].flags & kTermBH, tid, ra, rb,
-                               As[buf ^ 1], Bs[buf ^ 1]);
+        if (has_next) {
+            finish_stage<BM>(st);
+            store_stage<MIXED, BM>(tid, st, As[buf ^ 1], Bs[buf ^ 1]);
+        }
         __syncthreads();
         buf ^= 1;
         t = tn2;
         k0 = kn;
     }
 
-    // Epilogue: lane holds rows row_of(lane, r) of each 16 x 16 real block, real column lane%16.
+    // Epilogue: lane holds rows row_of(lane, r) of each 16 x 16 real block,
+    // real column lane%16 (component lane%2 of complex column lane%16 / 2).
     double* D = reinterpret_cast<double*>(op->D);
     const double2* C = op->C;
     const int ldd = op->ldd, ldc = op->ldc;
     const double2 beta = op->beta;
+    if (C) {
+        // all C loads first (clamped, unconditional), then the stores
+        double2 cv[MI][2][4];
+        const gptr_t Cp = (gptr_t)C;
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = i0 + wm * 32 + mi * 16 + Prec<MIXED>::row_of(lane, r);
-                const int jr = wn * 32 + ni * 16 + r16;
-                const int col = j0 + (jr >> 1);
-                const int comp = jr & 1;
-                if (row < m && col < n) {
-                    double v = (double)acc[mi][ni][r];
-                    if (C) {
-                        const double2 c = C[(size_t)row * ldc + col];
-                        v += comp ? (beta.x * c.y + beta.y * c.x) : (beta.x * c.x - beta.y * c.y);
-                    }
-                    D[2 * ((size_t)row * ldd + col) + comp] = v;
+                for (int r = 0; r < 4; ++r) {
+                    const int row = min(i0 + wm * (BM / 2) + mi * 16 + Prec<MIXED>::row_of(lane, r), m - 1);
+                    const int col = min(j0 + ((wn * 32 + ni * 16 + r16) >> 1), n - 1);
+                    cv[mi][ni][r] = Cp[(size_t)row * ldc + col];
                 }
-            }
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    asm volatile("" : "+v"(cv[mi][ni][r].x), "+v"(cv[mi][ni][r].y));
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = i0 + wm * (BM / 2) + mi * 16 + Prec<MIXED>::row_of(lane, r);
+                    const int col = j0 + ((wn * 32 + ni * 16 + r16) >> 1);
+                    const double2 c = cv[mi][ni][r];
+                    const double v = (double)acc[mi][ni][r] +
+                        (d ? (beta.x * c.y + beta.y * c.x) : (beta.x * c.x - beta.y * c.y));
+                    if (row < m && col < n) D[2 * ((size_t)row * ldd + col) + d] = v;
+                }
+    } else {
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = i0 + wm * (BM / 2) + mi * 16 + Prec<MIXED>::row_of(lane, r);
+                    const int col = j0 + ((wn * 32 + ni * 16 + r16) >> 1);
+                    if (row < m && col < n) D[2 * ((size_t)row * ldd + col) + d] = (double)acc[mi][ni][r];
+                }
+    }
 }
 
+// Tiles are counted in 64-row units by the scheduler; a launch whose
+// products give too few of them to fill the chip runs 32-row tiles instead
+// (twice as many workgroups).  tile_begin offsets are then doubled per op.
 int gemm_tiles(int m, int n) {
     return ((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN);
 }
@@ -232,9 +328,24 @@ int gemm_tiles_n(int n) { return (n + kBN - 1) / kBN; }
 hipError_t launch_gemm(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s) {
     if (nops <= 0 || total_tiles <= 0) return hipSuccess;
     if (mixed)
-        hipLaunchKernelGGL(zgemm_grouped<true>, dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
+        hipLaunchKernelGGL((zgemm_grouped<true, 64>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
     else
-        hipLaunchKernelGGL(zgemm_grouped<false>, dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
+        hipLaunchKernelGGL((zgemm_grouped<false, 64>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
+    return hipGetLastError();
+}
+
+// Same with 32-row tiles; tile_begin / tile counts of the ops must be in
+// 32-row units (gemm_tiles32).
+int gemm_tiles32(int m, int n) {
+    return ((m + 31) / 32) * ((n + kBN - 1) / kBN);
+}
+
+hipError_t launch_gemm32(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s) {
+    if (nops <= 0 || total_tiles <= 0) return hipSuccess;
+    if (mixed)
+        hipLaunchKernelGGL((zgemm_grouped<true, 32>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
+    else
+        hipLaunchKernelGGL((zgemm_grouped<false, 32>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
     return hipGetLastError();
 }
 

@@ -65,19 +65,29 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
 
     double2 P[R][NB];
     int used[R];
+    // all panel loads in flight together: indices clamped into the matrix,
+    // out-of-range entries zeroed after the loads complete
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = tid + q * T;
-        used[q] = 1;
+        const int r = min(tid + q * T, d - 1);
+        const double2* row = J.W + (size_t)r * d + j0;
+        used[q] = J.used[r];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) P[q][c] = make_double2(0.0, 0.0);
-        if (r < d) {
-            used[q] = J.used[r];
-            const double2* row = J.W + (size_t)r * d + j0;
+        for (int c = 0; c < NB; ++c) P[q][c] = row[min(c, nc - 1)];
+    }
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nc) P[q][c] = row[c];
-        }
+    for (int q = 0; q < R; ++q) {
+        asm volatile("" : "+v"(used[q]));
+#pragma unroll
+        for (int c = 0; c < NB; ++c) asm volatile("" : "+v"(P[q][c].x), "+v"(P[q][c].y));
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const bool rin = tid + q * T < d;
+        if (!rin) used[q] = 1;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (!rin || c >= nc) P[q][c] = make_double2(0.0, 0.0);
     }
 
 #pragma unroll
@@ -178,12 +188,30 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
         }
     }
     if (tid < nc) J.perm[j0 + tid] = piv[tid];
-    // Y: gathered pivot rows outside the panel (rows >= nc are zero)
-    for (int e = tid; e < NB * d; e += T) {
-        const int c = e / d, col = e - c * d;
-        double2 v = make_double2(0.0, 0.0);
-        if (c < nc && (col < j0 || col >= j0 + nc)) v = J.W[(size_t)piv[c] * d + col];
-        J.Y[e] = v;
+    // Y: gathered pivot rows outside the panel (rows >= nc are zero).  Eight
+    // loads per thread are issued before any is used.
+    constexpr int U = 8;
+    const int total = NB * d;
+    for (int base = 0; base < total; base += U * T) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = min(base + u * T + tid, total - 1);
+            const int c = e / d, col = e - c * d;
+            const int pr = piv[min(c, nc - 1)];
+            v[u] = J.W[(size_t)pr * d + col];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) asm volatile("" : "+v"(v[u].x), "+v"(v[u].y));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * T + tid;
+            if (e < total) {
+                const int c = e / d, col = e - c * d;
+                const bool keep = c < nc && (col < j0 || col >= j0 + nc);
+                J.Y[e] = keep ? v[u] : make_double2(0.0, 0.0);
+            }
+        }
     }
 }
 

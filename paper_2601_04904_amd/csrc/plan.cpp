@@ -45,6 +45,8 @@ hipError_t launch_inv_panel(const InvJob* d_jobs, int njobs, int rows_per_thread
                             DevStatus* status, hipStream_t s);
 hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
 hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s);
+hipError_t launch_gemm32(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s);
+int gemm_tiles32(int m, int n);
 }  // namespace btsq
 
 using namespace btsq;
@@ -80,6 +82,8 @@ struct OpRec {
     int tag = 0;                                   // inverse: block id
     std::vector<std::pair<double2, MatRef>> ins;   // add
     int level = 0;
+    int cls = 0;          // 1: critical A-chain stream, 0: main stream
+    int wait_other = -1;  // highest level of a predecessor on the other stream
 };
 
 enum Mode { MODE_FACTOR = 0, MODE_SQ = 1, MODE_BOTH = 2 };
@@ -211,6 +215,7 @@ struct Builder {
     std::vector<OpRec> ops;
     std::unordered_map<uint64_t, MatRef> curA, curB, wsA, wsB, xR, xL;
     double flops = 0.0;
+    int cur_cls = 0;      // stream class of the operations being emitted
 
     bool emitA() const { return mode == MODE_FACTOR || mode == MODE_BOTH; }
     bool emitB() const { return mode == MODE_SQ || mode == MODE_BOTH; }
@@ -313,6 +318,7 @@ struct Builder {
         op.beta = beta;
         op.terms = kept;
         op.mixed = mixed;
+        op.cls = cur_cls;
         for (auto& t : kept) {
             const int k = t.ah ? t.A.r : t.A.c;
             flops += 8.0 * Dst.r * Dst.c * k;
@@ -327,6 +333,7 @@ struct Builder {
         op.C = src;
         op.D = dst;
         op.tag = tag;
+        op.cls = cur_cls;
         flops += 8.0 * (double)dst.r * dst.r * dst.r;
         ops.push_back(op);
     }
@@ -336,6 +343,7 @@ struct Builder {
         OpRec op;
         op.kind = K_ADD;
         op.D = Dst;
+        op.cls = cur_cls;
         for (auto& x : ins)
             if (x.second.ok()) op.ins.push_back(x);
         ops.push_back(op);
@@ -354,6 +362,7 @@ struct Builder {
         const int dk = D.dim(k);
         const double2 one = cplx(1), mone = cplx(-1), zero = cplx(0);
         r.S = alloc(dk, dk);
+        cur_cls = 1;   // the A-chain: inverse, T and Schur updates
         inv(emitA(), cur(false, k, k, tip_tag(k, k, part_tag)), r.S, k);
         for (int u : N) {
             r.Auk[u] = cur(false, u, k, 0);
@@ -370,6 +379,7 @@ struct Builder {
                 curA[key3(u, v, tg)] = dst;
             }
         // B-chain
+        cur_cls = 0;
         MatRef Bkk = cur(true, k, k, tip_tag(k, k, part_tag));
         r.Z = alloc(dk, dk);
         r.SB = alloc(dk, dk);
@@ -482,7 +492,9 @@ struct Builder {
                     ins.push_back({cplx(1), cur(isB, t, t, 0)});
                     for (int p = 0; p < P; ++p) ins.push_back({cplx(1), cur(isB, t, t, p + 1)});
                     MatRef dst = work_slot(isB, t, t, 0);
+                    cur_cls = isB ? 0 : 1;
                     add(isB ? emitB() : emitA(), dst, ins);
+                    cur_cls = 0;
                     (isB ? curB : curA)[key3(t, t, 0)] = dst;
                 }
             }
@@ -501,14 +513,16 @@ struct Builder {
     }
 };
 
-// Dependency levels on whole blocks.
+// Dependency levels on whole blocks (read-after-write, write-after-read,
+// write-after-write).  Also records, per operation, the highest level of a
+// predecessor that runs on the other stream.
 int levelize(std::vector<OpRec>& ops) {
-    std::unordered_map<uintptr_t, int> lastW, lastR;
-    auto getW = [&](const MatRef& m) { auto it = lastW.find((uintptr_t)m.p); return it == lastW.end() ? -1 : it->second; };
-    auto getR = [&](const MatRef& m) { auto it = lastR.find((uintptr_t)m.p); return it == lastR.end() ? -1 : it->second; };
+    struct BufInfo { int wlevel = -1, wcls = 0; int rlevel[2] = {-1, -1}; };
+    std::unordered_map<uintptr_t, BufInfo> info;
     int maxl = -1;
+    std::vector<MatRef> reads;
     for (auto& op : ops) {
-        std::vector<MatRef> reads;
+        reads.clear();
         if (op.kind == K_GEMM) {
             if (op.C.ok()) reads.push_back(op.C);
             for (auto& t : op.terms) { reads.push_back(t.A); reads.push_back(t.B); }
@@ -517,13 +531,37 @@ int levelize(std::vector<OpRec>& ops) {
         } else {
             for (auto& x : op.ins) reads.push_back(x.second);
         }
-        int lvl = 0;
-        for (auto& r : reads) lvl = std::max(lvl, getW(r) + 1);
-        lvl = std::max(lvl, getW(op.D) + 1);
-        lvl = std::max(lvl, getR(op.D) + 1);
+        int lvl = 0, other = -1;
+        for (auto& r : reads) {
+            auto it = info.find((uintptr_t)r.p);
+            if (it == info.end() || it->second.wlevel < 0) continue;
+            lvl = std::max(lvl, it->second.wlevel + 1);
+            if (it->second.wcls != op.cls) other = std::max(other, it->second.wlevel);
+        }
+        {
+            auto it = info.find((uintptr_t)op.D.p);
+            if (it != info.end()) {
+                const BufInfo& bi = it->second;
+                if (bi.wlevel >= 0) {
+                    lvl = std::max(lvl, bi.wlevel + 1);
+                    if (bi.wcls != op.cls) other = std::max(other, bi.wlevel);
+                }
+                for (int c = 0; c < 2; ++c)
+                    if (bi.rlevel[c] >= 0) {
+                        lvl = std::max(lvl, bi.rlevel[c] + 1);
+                        if (c != op.cls) other = std::max(other, bi.rlevel[c]);
+                    }
+            }
+        }
         op.level = lvl;
-        lastW[(uintptr_t)op.D.p] = lvl;
-        for (auto& r : reads) lastR[(uintptr_t)r.p] = std::max(getR(r), lvl);
+        op.wait_other = other;
+        BufInfo& w = info[(uintptr_t)op.D.p];
+        w.wlevel = lvl;
+        w.wcls = op.cls;
+        for (auto& r : reads) {
+            BufInfo& bi = info[(uintptr_t)r.p];
+            bi.rlevel[op.cls] = std::max(bi.rlevel[op.cls], lvl);
+        }
         maxl = std::max(maxl, lvl);
     }
     return maxl + 1;
@@ -538,7 +576,33 @@ struct Launch {
     int maxd;         // inverse: max dim; panel: rows per thread
     int panel;
     size_t maxelems;  // add
+    double flops = 0; // algorithmic work of the launch
+    double bytes = 0;
+    int bm = 64;      // gemm: tile rows
+    int cls = 0;      // stream class
+    int level = 0;
+    int wait_level = -1;  // wait for the other stream up to this level
+    int wait_event = -1;  // event slot to wait on before the launch
+    int rec_event = -1;   // event slot to record after the launch
 };
+
+// Launches with fewer 64-row tiles than this run 32-row tiles.
+constexpr int kSmallLaunchTiles = 512;
+
+// Algorithmic flops and HBM bytes of a grouped product launch.
+void gemm_work(const GemmOp* ops, int n, double& flops, double& bytes) {
+    flops = 0;
+    bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        const GemmOp& g = ops[i];
+        double mn = (double)g.m * g.n;
+        bytes += 16.0 * mn * (g.C ? 2.0 : 1.0);
+        for (int t = 0; t < g.nterms; ++t) {
+            flops += 8.0 * mn * g.t[t].k;
+            bytes += 16.0 * ((double)g.m * g.t[t].k + (double)g.t[t].k * g.n);
+        }
+    }
+}
 
 struct Program {
     std::vector<GemmOp> gemm;
@@ -548,6 +612,7 @@ struct Program {
     size_t inv_scratch_bytes = 0;   // scratch the inverses need (max over levels)
     double flops = 0.0;
     int levels = 0;
+    int n_events = 0;               // cross-stream events the launches use
 };
 
 GemmOp make_gemm_op(const OpRec& o) {
@@ -577,7 +642,21 @@ GemmOp make_gemm_op(const OpRec& o) {
     return g;
 }
 
+// Retile a grouped product launch with 32-row tiles when it has few tiles.
+void choose_tiles(Program& pg, Launch& L) {
+    if (L.tiles >= kSmallLaunchTiles) return;
+    int tiles = 0;
+    for (int i = 0; i < L.count; ++i) {
+        GemmOp& g = pg.gemm[L.off + i];
+        g.tile_begin = tiles;
+        tiles += gemm_tiles32(g.m, g.n);
+    }
+    L.tiles = tiles;
+    L.bm = 32;
+}
+
 // Turn levelled operations into typed device arrays and a launch list.
+// Launches are ordered by level and, within a level, critical stream first.
 // inv_pool: base of the inverse scratch pool (may be fake in dry runs).
 Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
     Program pg;
@@ -585,110 +664,179 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
     std::vector<std::vector<int>> bylevel(nlevels);
     for (int i = 0; i < (int)ops.size(); ++i) bylevel[ops[i].level].push_back(i);
     const size_t NB = kInvNB;
+    auto mk = [&](int type, size_t off, int count, int tiles, int mixed, int maxd, int panel,
+                  size_t maxe, int cls, int level, int wait) {
+        Launch L{type, off, count, tiles, mixed, maxd, panel, maxe};
+        L.cls = cls;
+        L.level = level;
+        L.wait_level = wait;
+        return L;
+    };
     for (int L = 0; L < nlevels; ++L) {
-        // inverses (grouped by rows per thread of the panel kernel)
-        std::vector<int> invs;
-        for (int i : bylevel[L]) if (ops[i].kind == K_INV) invs.push_back(i);
-        if (!invs.empty()) {
-            std::stable_sort(invs.begin(), invs.end(), [&](int x, int y) {
-                return (ops[x].D.r > 512) < (ops[y].D.r > 512);
-            });
-            size_t poff = 0;
-            const size_t first = pg.inv.size();
-            int maxd = 0;
-            for (int i : invs) {
-                const OpRec& o = ops[i];
-                const int d = o.D.r;
-                maxd = std::max(maxd, d);
-                InvJob j;
-                memset(&j, 0, sizeof j);
-                j.src = o.C.p;
-                j.dst = o.D.p;
-                j.d = d;
-                j.tag = o.tag;
-                auto take = [&](size_t bytes) { poff = (poff + 255) & ~(size_t)255; char* p = inv_pool + poff; poff += bytes; return p; };
-                j.W = reinterpret_cast<double2*>(take((size_t)d * d * sizeof(double2)));
-                j.Mm = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
-                j.Y = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
-                j.perm = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
-                j.used = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
-                pg.inv.push_back(j);
+        for (int cls = 1; cls >= 0; --cls) {
+            // inverses (grouped by rows per thread of the panel kernel)
+            std::vector<int> invs;
+            int wait = -1;
+            for (int i : bylevel[L])
+                if (ops[i].kind == K_INV && ops[i].cls == cls) { invs.push_back(i); wait = std::max(wait, ops[i].wait_other); }
+            if (!invs.empty()) {
+                std::stable_sort(invs.begin(), invs.end(), [&](int x, int y) {
+                    return (ops[x].D.r > 512) < (ops[y].D.r > 512);
+                });
+                size_t poff = 0;
+                const size_t first = pg.inv.size();
+                int maxd = 0;
+                for (int i : invs) {
+                    const OpRec& o = ops[i];
+                    const int d = o.D.r;
+                    maxd = std::max(maxd, d);
+                    InvJob j;
+                    memset(&j, 0, sizeof j);
+                    j.src = o.C.p;
+                    j.dst = o.D.p;
+                    j.d = d;
+                    j.tag = o.tag;
+                    auto take = [&](size_t bytes) { poff = (poff + 255) & ~(size_t)255; char* p = inv_pool + poff; poff += bytes; return p; };
+                    j.W = reinterpret_cast<double2*>(take((size_t)d * d * sizeof(double2)));
+                    j.Mm = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
+                    j.Y = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
+                    j.perm = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
+                    j.used = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
+                    pg.inv.push_back(j);
+                }
+                pg.inv_scratch_bytes = std::max(pg.inv_scratch_bytes, poff + 256);
+                const int nj = (int)invs.size();
+                int n1 = 0;
+                for (int i : invs) if (ops[i].D.r <= 512) ++n1;
+                pg.launches.push_back(mk(1, first, nj, 0, 0, maxd, 0, 0, cls, L, wait));
+                const int npanels = (maxd + kInvNB - 1) / kInvNB;
+                for (int p = 0; p < npanels; ++p) {
+                    if (n1 > 0) pg.launches.push_back(mk(2, first, n1, 0, 0, 1, p, 0, cls, L, -1));
+                    if (nj - n1 > 0) pg.launches.push_back(mk(2, first + n1, nj - n1, 0, 0, 2, p, 0, cls, L, -1));
+                    // trailing update W += Mm Y for the jobs that still have this panel
+                    const size_t g0 = pg.gemm.size();
+                    int tiles = 0;
+                    for (int q = 0; q < nj; ++q) {
+                        const InvJob& j = pg.inv[first + q];
+                        if (p * kInvNB >= j.d) continue;
+                        GemmOp g;
+                        memset(&g, 0, sizeof g);
+                        g.D = j.W;
+                        g.C = j.W;
+                        g.ldd = g.ldc = j.d;
+                        g.m = g.n = j.d;
+                        g.nterms = 1;
+                        g.tiles_n = gemm_tiles_n(j.d);
+                        g.tile_begin = tiles;
+                        g.beta = cplx(1);
+                        g.t[0].A = j.Mm;
+                        g.t[0].B = j.Y;
+                        g.t[0].lda = kInvNB;
+                        g.t[0].ldb = j.d;
+                        g.t[0].k = kInvNB;
+                        g.t[0].alpha = cplx(1);
+                        tiles += gemm_tiles(j.d, j.d);
+                        pg.gemm.push_back(g);
+                    }
+                    Launch gl = mk(0, g0, (int)(pg.gemm.size() - g0), tiles, 0, 0, 0, 0, cls, L, -1);
+                    choose_tiles(pg, gl);
+                    pg.launches.push_back(gl);
+                }
+                pg.launches.push_back(mk(3, first, nj, 0, 0, maxd, 0, 0, cls, L, -1));
             }
-            pg.inv_scratch_bytes = std::max(pg.inv_scratch_bytes, poff + 256);
-            const int nj = (int)invs.size();
-            int n1 = 0;
-            for (int i : invs) if (ops[i].D.r <= 512) ++n1;
-            pg.launches.push_back(Launch{1, first, nj, 0, 0, maxd, 0, 0});
-            const int npanels = (maxd + kInvNB - 1) / kInvNB;
-            for (int p = 0; p < npanels; ++p) {
-                if (n1 > 0) pg.launches.push_back(Launch{2, first, n1, 0, 0, 1, p, 0});
-                if (nj - n1 > 0) pg.launches.push_back(Launch{2, first + n1, nj - n1, 0, 0, 2, p, 0});
-                // trailing update W += Mm Y for the jobs that still have this panel
+            // products, per precision
+            for (int mx = 0; mx < 2; ++mx) {
                 const size_t g0 = pg.gemm.size();
-                int tiles = 0;
-                for (int q = 0; q < nj; ++q) {
-                    const InvJob& j = pg.inv[first + q];
-                    if (p * kInvNB >= j.d) continue;
-                    GemmOp g;
-                    memset(&g, 0, sizeof g);
-                    g.D = j.W;
-                    g.C = j.W;
-                    g.ldd = g.ldc = j.d;
-                    g.m = g.n = j.d;
-                    g.nterms = 1;
-                    g.tiles_n = gemm_tiles_n(j.d);
+                int tiles = 0, gw = -1;
+                for (int i : bylevel[L]) {
+                    const OpRec& o = ops[i];
+                    if (o.kind != K_GEMM || (int)o.mixed != mx || o.cls != cls) continue;
+                    GemmOp g = make_gemm_op(o);
                     g.tile_begin = tiles;
-                    g.beta = cplx(1);
-                    g.t[0].A = j.Mm;
-                    g.t[0].B = j.Y;
-                    g.t[0].lda = kInvNB;
-                    g.t[0].ldb = j.d;
-                    g.t[0].k = kInvNB;
-                    g.t[0].alpha = cplx(1);
-                    tiles += gemm_tiles(j.d, j.d);
+                    tiles += gemm_tiles(g.m, g.n);
                     pg.gemm.push_back(g);
+                    gw = std::max(gw, o.wait_other);
                 }
-                pg.launches.push_back(Launch{0, g0, (int)(pg.gemm.size() - g0), tiles, 0, 0, 0, 0});
-            }
-            pg.launches.push_back(Launch{3, first, nj, 0, 0, maxd, 0, 0});
-        }
-        // products, per precision
-        for (int mx = 0; mx < 2; ++mx) {
-            const size_t g0 = pg.gemm.size();
-            int tiles = 0;
-            for (int i : bylevel[L]) {
-                const OpRec& o = ops[i];
-                if (o.kind != K_GEMM || (int)o.mixed != mx) continue;
-                GemmOp g = make_gemm_op(o);
-                g.tile_begin = tiles;
-                tiles += gemm_tiles(g.m, g.n);
-                pg.gemm.push_back(g);
-            }
-            if (pg.gemm.size() > g0)
-                pg.launches.push_back(Launch{0, g0, (int)(pg.gemm.size() - g0), tiles, mx, 0, 0, 0});
-        }
-        // sums
-        {
-            const size_t a0 = pg.add.size();
-            size_t maxe = 0;
-            for (int i : bylevel[L]) {
-                const OpRec& o = ops[i];
-                if (o.kind != K_ADD) continue;
-                AddOp a;
-                memset(&a, 0, sizeof a);
-                a.D = o.D.p;
-                a.nin = (int)o.ins.size();
-                a.rows = o.D.r;
-                a.cols = o.D.c;
-                for (int q = 0; q < a.nin && q < kMaxAdd; ++q) {
-                    a.X[q] = o.ins[q].second.p;
-                    a.c[q] = o.ins[q].first;
+                if (pg.gemm.size() > g0) {
+                    Launch gl = mk(0, g0, (int)(pg.gemm.size() - g0), tiles, mx, 0, 0, 0, cls, L, gw);
+                    choose_tiles(pg, gl);
+                    pg.launches.push_back(gl);
                 }
-                maxe = std::max(maxe, (size_t)a.rows * a.cols);
-                pg.add.push_back(a);
             }
-            if (pg.add.size() > a0)
-                pg.launches.push_back(Launch{4, a0, (int)(pg.add.size() - a0), 0, 0, 0, 0, maxe});
+            // sums
+            {
+                const size_t a0 = pg.add.size();
+                size_t maxe = 0;
+                int aw = -1;
+                for (int i : bylevel[L]) {
+                    const OpRec& o = ops[i];
+                    if (o.kind != K_ADD || o.cls != cls) continue;
+                    AddOp a;
+                    memset(&a, 0, sizeof a);
+                    a.D = o.D.p;
+                    a.nin = (int)o.ins.size();
+                    a.rows = o.D.r;
+                    a.cols = o.D.c;
+                    for (int q = 0; q < a.nin && q < kMaxAdd; ++q) {
+                        a.X[q] = o.ins[q].second.p;
+                        a.c[q] = o.ins[q].first;
+                    }
+                    maxe = std::max(maxe, (size_t)a.rows * a.cols);
+                    pg.add.push_back(a);
+                    aw = std::max(aw, o.wait_other);
+                }
+                if (pg.add.size() > a0)
+                    pg.launches.push_back(mk(4, a0, (int)(pg.add.size() - a0), 0, 0, 0, 0, maxe, cls, L, aw));
+            }
+        }
+    }
+    // cross-stream events: a launch that waits for level W of the other stream
+    // waits on an event recorded after that stream's last launch at level <= W
+    {
+        std::vector<int> last_idx[2];
+        std::vector<int> last_of_level[2];
+        for (int c = 0; c < 2; ++c) last_of_level[c].assign(nlevels, -1);
+        for (int i = 0; i < (int)pg.launches.size(); ++i) {
+            const Launch& L = pg.launches[i];
+            last_of_level[L.cls][L.level] = i;
+        }
+        for (int c = 0; c < 2; ++c)
+            for (int l = 1; l < nlevels; ++l)
+                if (last_of_level[c][l] < 0) last_of_level[c][l] = last_of_level[c][l - 1];
+        for (auto& L : pg.launches) {
+            if (L.wait_level < 0) continue;
+            const int o = 1 - L.cls;
+            const int src = last_of_level[o][std::min(L.wait_level, nlevels - 1)];
+            if (src < 0) continue;
+            Launch& S = pg.launches[src];
+            if (S.rec_event < 0) S.rec_event = pg.n_events++;
+            L.wait_event = S.rec_event;
+        }
+    }
+    for (Launch& L : pg.launches) {
+        if (L.type == 0) {
+            gemm_work(pg.gemm.data() + L.off, L.count, L.flops, L.bytes);
+        } else if (L.type == 2) {
+            // panel: each eliminated column updates the panel rows (8 flops per complex
+            // multiply-add, nb columns): d * nb * nb complex MACs per job
+            for (int q = 0; q < L.count; ++q) {
+                const InvJob& j = pg.inv[L.off + q];
+                if (L.panel * kInvNB >= j.d) continue;
+                const double nc = std::min(kInvNB, j.d - L.panel * kInvNB);
+                L.flops += 8.0 * j.d * nc * nc;
+                L.bytes += 16.0 * (2.0 * j.d * nc + 2.0 * j.d * kInvNB + 2.0 * kInvNB * j.d);
+            }
+        } else if (L.type == 1 || L.type == 3) {
+            for (int q = 0; q < L.count; ++q) {
+                const InvJob& j = pg.inv[L.off + q];
+                L.bytes += 32.0 * j.d * j.d;
+            }
+        } else if (L.type == 4) {
+            for (int q = 0; q < L.count; ++q) {
+                const AddOp& a = pg.add[L.off + q];
+                L.flops += 8.0 * a.rows * a.cols * a.nin;
+                L.bytes += 16.0 * a.rows * a.cols * (a.nin + 1);
+            }
         }
     }
     return pg;
@@ -703,7 +851,9 @@ struct bt_si_sq_plan {
     Dims D{};
     bt_desc desc{};
     std::vector<int> bounds;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // the caller's stream (main stream)
+    hipStream_t astream = nullptr;    // internal stream for the critical A-chain
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;
     char* ws = nullptr;
     size_t ws_main = 0;        // bytes of block slots
     char* inv_pool = nullptr;
@@ -722,10 +872,18 @@ struct bt_si_sq_plan {
         char* dev = nullptr;
         size_t dev_bytes = 0;
         size_t off_gemm = 0, off_inv = 0, off_add = 0;
+        std::vector<hipEvent_t> events;   // cross-stream events of the launch list
     } cache[3];
     char* host_stage = nullptr;
     size_t host_stage_bytes = 0;
     hipEvent_t upload_done = nullptr;
+    // profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending { int kind; hipEvent_t a, b; double flops, bytes; };
+    std::vector<Pending> pending;
+    size_t ev_used = 0;
+    bt_kernel_stat stats[BT_KERNEL_COUNT];
 };
 
 namespace {
@@ -781,24 +939,92 @@ void dry_run(const Dims& D, const std::vector<int>& bounds, bool mixed, size_t& 
     inv_bytes = pg.inv_scratch_bytes;
 }
 
+hipEvent_t next_event(bt_si_sq_plan* h) {
+    if (h->ev_used == h->ev_pool.size()) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+        h->ev_pool.push_back(ev);
+    }
+    return h->ev_pool[h->ev_used++];
+}
+
+void collect_profile(bt_si_sq_plan* h) {
+    for (auto& p : h->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
+        bt_kernel_stat& s = h->stats[p.kind];
+        s.kind = p.kind;
+        s.launches += 1;
+        s.total_ms += ms;
+        s.flops += p.flops;
+        s.bytes += p.bytes;
+    }
+    h->pending.clear();
+    h->ev_used = 0;
+}
+
+int kernel_kind(const Launch& L) {
+    switch (L.type) {
+        case 0: return L.mixed ? BT_KERNEL_PRODUCT_MIXED : BT_KERNEL_PRODUCT_FP64;
+        case 1: return BT_KERNEL_INV_INIT;
+        case 2: return BT_KERNEL_INV_PANEL;
+        case 3: return BT_KERNEL_INV_FINISH;
+        default: return BT_KERNEL_SUM;
+    }
+}
+
 hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
     const Program& pg = c.prog;
     GemmOp* dg = reinterpret_cast<GemmOp*>(c.dev + c.off_gemm);
     InvJob* dj = reinterpret_cast<InvJob*>(c.dev + c.off_inv);
     AddOp* da = reinterpret_cast<AddOp*>(c.dev + c.off_add);
     hipError_t e = hipSuccess;
+    if (h->profiling && h->ev_used + 2 * pg.launches.size() > 200000) {
+        // bound the number of outstanding events: fold in what has finished
+        hipStreamSynchronize(h->stream);
+        collect_profile(h);
+    }
+    // the critical stream starts after everything already queued on the main stream
+    e = hipEventRecord(h->ev_start, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->astream, h->ev_start, 0);
+    if (e != hipSuccess) return e;
     for (const Launch& L : pg.launches) {
+        hipStream_t s = L.cls ? h->astream : h->stream;
+        if (L.wait_event >= 0) {
+            e = hipStreamWaitEvent(s, c.events[L.wait_event], 0);
+            if (e != hipSuccess) return e;
+        }
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (h->profiling) {
+            ea = next_event(h);
+            eb = next_event(h);
+            if (ea) hipEventRecord(ea, s);
+        }
         switch (L.type) {
-            case 0: e = launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, h->stream); break;
-            case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, h->stream); break;
-            case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, h->status, h->stream); break;
-            case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, h->stream); break;
-            case 4: e = launch_add(da + L.off, L.count, L.maxelems, h->stream); break;
+            case 0:
+                e = L.bm == 32 ? launch_gemm32(dg + L.off, L.count, L.tiles, L.mixed != 0, s)
+                               : launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s);
+                break;
+            case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
+            case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, h->status, s); break;
+            case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
+            case 4: e = launch_add(da + L.off, L.count, L.maxelems, s); break;
         }
         if (e != hipSuccess) return e;
+        if (h->profiling && ea && eb) {
+            hipEventRecord(eb, s);
+            h->pending.push_back({kernel_kind(L), ea, eb, L.flops, L.bytes});
+        }
+        if (L.rec_event >= 0) {
+            e = hipEventRecord(c.events[L.rec_event], s);
+            if (e != hipSuccess) return e;
+        }
     }
+    // the solve is complete when the main stream is
+    e = hipEventRecord(h->ev_end, h->astream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_end, 0);
     h->last_launches = (int32_t)pg.launches.size();
-    return hipSuccess;
+    return e;
 }
 
 bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const bt_blocks* A, const bt_blocks* B,
@@ -860,6 +1086,14 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const bt_blocks* A, const
         if (e != hipSuccess) return hip_err(h, e, "hipMemcpyAsync(op list)");
         e = hipEventRecord(h->upload_done, h->stream);
         if (e != hipSuccess) return hip_err(h, e, "hipEventRecord");
+        for (auto ev : c.events) hipEventDestroy(ev);
+        c.events.clear();
+        for (int i = 0; i < pg.n_events; ++i) {
+            hipEvent_t ev;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_err(h, e, "hipEventCreate");
+            c.events.push_back(ev);
+        }
         c.prog = std::move(pg);
         c.off_gemm = 0;
         c.off_inv = off_inv;
@@ -952,6 +1186,9 @@ bt_status bt_si_sq_create(const bt_desc* desc, void* hip_stream, bt_si_sq_handle
     DevStatus z{0, 0};
     e = hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->astream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         hipFree(h->ws); hipFree(h->inv_pool); hipFree(h->status);
         return hip_err(nullptr, e, "create");
@@ -1026,10 +1263,17 @@ bt_status bt_si_sq_sync(bt_si_sq_handle h) {
 bt_status bt_si_sq_destroy(bt_si_sq_handle h) {
     if (!h) return BT_OK;
     hipStreamSynchronize(h->stream);
-    for (auto& c : h->cache)
+    hipStreamSynchronize(h->astream);
+    for (auto& c : h->cache) {
         if (c.dev) hipFree(c.dev);
+        for (auto ev : c.events) hipEventDestroy(ev);
+    }
+    if (h->ev_start) hipEventDestroy(h->ev_start);
+    if (h->ev_end) hipEventDestroy(h->ev_end);
+    if (h->astream) hipStreamDestroy(h->astream);
     if (h->host_stage) hipHostFree(h->host_stage);
     if (h->upload_done) hipEventDestroy(h->upload_done);
+    for (auto ev : h->ev_pool) hipEventDestroy(ev);
     hipFree(h->ws);
     hipFree(h->inv_pool);
     hipFree(h->status);
@@ -1042,6 +1286,30 @@ const char* bt_si_sq_last_error(bt_si_sq_handle h) {
 }
 
 int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h) { return h ? h->last_launches : 0; }
+
+bt_status bt_si_sq_profile(bt_si_sq_handle h, int32_t enable) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
+    h->pending.clear();
+    h->ev_used = 0;
+    for (int k = 0; k < BT_KERNEL_COUNT; ++k) h->stats[k] = bt_kernel_stat{k, 0, 0.0, 0.0, 0.0};
+    h->profiling = enable != 0;
+    return BT_OK;
+}
+
+bt_status bt_si_sq_profile_stats(bt_si_sq_handle h, bt_kernel_stat* out, int32_t max_entries,
+                                 int32_t* count) {
+    if (!h || !count || (max_entries > 0 && !out)) return set_err(h, BT_ERR_INVALID, "bad arguments");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
+    collect_profile(h);
+    int32_t c = 0;
+    for (int k = 0; k < BT_KERNEL_COUNT; ++k)
+        if (h->stats[k].launches > 0 && c < max_entries) out[c++] = h->stats[k];
+    *count = c;
+    return BT_OK;
+}
 
 }  // extern "C"
 
@@ -1133,7 +1401,10 @@ bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t c
     for (const Launch& L : pg.launches) {
         if (e != hipSuccess) break;
         switch (L.type) {
-            case 0: e = launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s); break;
+            case 0:
+                e = L.bm == 32 ? launch_gemm32(dg + L.off, L.count, L.tiles, L.mixed != 0, s)
+                               : launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s);
+                break;
             case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
             case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, st, s); break;
             case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
@@ -1156,3 +1427,36 @@ bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t c
 }
 
 }  // extern "C"
+
+extern "C" size_t bt_si_sq_diag_schedule(const bt_desc* desc, char* out, size_t cap) {
+    std::vector<int> bounds;
+    std::string msg;
+    if (!desc_bounds(desc, bounds, msg)) { g_last_error = msg; return 0; }
+    Builder bd;
+    bd.D = Dims{desc->n, desc->b, desc->a};
+    bd.bounds = bounds;
+    bd.mode = MODE_BOTH;
+    bd.mixed_bulk = desc->precision == BT_MIXED;
+    bd.ws = reinterpret_cast<char*>((uintptr_t)1 << 40);
+    bd.build();
+    const int nl = levelize(bd.ops);
+    std::vector<int> ng(nl), nt(nl), ni(nl), na(nl), nc1(nl);
+    for (auto& o : bd.ops) {
+        if (o.kind == K_GEMM) { ng[o.level]++; nt[o.level] += gemm_tiles(o.D.r, o.D.c); }
+        else if (o.kind == K_INV) ni[o.level]++;
+        else na[o.level]++;
+        if (o.cls == 1) nc1[o.level]++;
+    }
+    std::string txt;
+    char line[128];
+    for (int L = 0; L < nl; ++L) {
+        snprintf(line, sizeof line, "%d %d %d %d %d %d\n", L, ng[L], nt[L], ni[L], na[L], nc1[L]);
+        txt += line;
+    }
+    if (out && cap > 0) {
+        size_t c = std::min(cap - 1, txt.size());
+        memcpy(out, txt.data(), c);
+        out[c] = 0;
+    }
+    return txt.size() + 1;
+}

@@ -137,6 +137,18 @@ class Solver:
     def last_launch_count(self) -> int:
         return int(_lib.lib().bt_si_sq_last_launch_count(self._h))
 
+    def profile(self, enable: bool = True):
+        check(_lib.lib().bt_si_sq_profile(self._h, int(bool(enable))), self._h)
+
+    def profile_stats(self):
+        """{kernel name: dict(launches, total_ms, flops, bytes)} since profile(True)."""
+        arr = (_lib.bt_kernel_stat * 8)()
+        cnt = C.c_int32()
+        check(_lib.lib().bt_si_sq_profile_stats(self._h, arr, 8, C.byref(cnt)), self._h)
+        return {_lib.KERNEL_NAMES[arr[i].kind]: dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                                      flops=arr[i].flops, bytes=arr[i].bytes)
+                for i in range(cnt.value)}
+
     def destroy(self):
         if getattr(self, "_h", None):
             _lib.lib().bt_si_sq_destroy(self._h)
