@@ -98,6 +98,122 @@ def cpu_baseline(A, B, seconds, XR_gpu, XL_gpu):
                        f"(NumPy complex128, {t_total:.1f} s)"), (errR, errL)
 
 
+def bench_batch(args, torch, S):
+    """Uneven batched energy sweep: mixed batched vs FP64 batched vs plain per-instance RGF."""
+    from paper_2601_04904_amd.synth import batch_specs
+    from paper_2601_04904_amd.synth_device import gen_problem_device
+    specs_all = batch_specs(512)
+    specs = specs_all[: args.batch_count]
+    log(f"[bench] batch of {len(specs)} uneven instances (first of the 512-instance sweep)")
+    probs = [gen_problem_device(sp["n"], sp["b"], sp["a"], sp["E"], sp["eta"], sp["seed"]) for sp in specs]
+    torch.cuda.synchronize()
+    flops = sum(S.flops(sp["n"], sp["b"], sp["a"], 1)[0] for sp in specs)
+
+    def run_batched(precision, waves):
+        out = {}
+        t_total = 0.0
+        errs, fbs = [], []
+        for w0 in range(0, len(specs), waves):
+            sub = list(range(w0, min(len(specs), w0 + waves)))
+            wspecs = [dict(n=specs[i]["n"], b=specs[i]["b"], a=specs[i]["a"], precision=precision) for i in sub]
+            XR = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
+            XL = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
+            bs = S.BatchSolver(wspecs)
+            A = [probs[i][0] for i in sub]
+            B = [probs[i][1] for i in sub]
+            bs.solve(A, B, XR, XL)   # warm-up: builds and uploads the schedule
+            bs.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, f = bs.solve(A, B, XR, XL)
+            bs.sync()
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t0
+            errs += e
+            fbs += f
+            bs.destroy()
+            del XR, XL
+        out["solves_per_s"] = round(len(specs) / t_total, 3)
+        out["tflops_executed"] = round(flops / t_total / 1e12, 3)
+        out["seconds"] = round(t_total, 3)
+        if precision == S.BT_MIXED:
+            out["max_err_estimate"] = max(errs)
+            out["fp64_fallbacks"] = int(sum(fbs))
+        return out
+
+    mixed = run_batched(S.BT_MIXED, args.batch_wave)
+    log(f"[bench] mixed batched: {mixed}")
+    fp64 = run_batched(S.BT_FP64, args.batch_wave)
+    log(f"[bench] fp64 batched: {fp64}")
+    # plain RGF: FP64, one instance at a time, one launch per block product, one stream
+    nplain = min(len(specs), args.plain_count)
+    t_plain = 0.0
+    for i in range(nplain):
+        sp = specs[i]
+        sol = S.Solver(sp["n"], sp["b"], sp["a"], flags=S.BT_PLAIN)
+        XR, XL = S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]), S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"])
+        sol.solve(probs[i][0], probs[i][1], XR, XL)
+        sol.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol.solve(probs[i][0], probs[i][1], XR, XL)
+        sol.sync()
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        sol.destroy()
+    plain = dict(solves_per_s=round(nplain / t_plain, 3), instances=nplain)
+    log(f"[bench] plain RGF: {plain}")
+    out = {
+        "metric": METRIC, "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * len(specs) / mixed["solves_per_s"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": f"batch_{len(specs)}_uneven", "n": "U{16..96}", "b": "U{64..384}",
+                   "a": "U{0,128,256}", "eta": 1e-3, "wave": args.batch_wave},
+        "mixed_batched": mixed, "fp64_batched": fp64, "plain_rgf": plain,
+        "mixed_vs_plain_rgf": round(mixed["solves_per_s"] / plain["solves_per_s"], 3),
+        "pct_fp32_peak_mixed_executed": round(100 * mixed["tflops_executed"] / FP32_PEAK_TFLOPS, 2),
+        "pct_fp64_peak_fp64_executed": round(100 * fp64["tflops_executed"] / FP64_PEAK_TFLOPS, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, torch, S):
+    """Poisson serving trace through the continuous-batching engine vs plain RGF."""
+    from paper_2601_04904_amd import serving
+    from paper_2601_04904_amd.synth import serving_trace
+    trace = serving_trace(args.requests, rate=args.rate, seed=0,
+                          n_range=(16, args.serve_max_n), b_choices=tuple(range(128, args.serve_max_b + 1, 64)))
+    reqs = serving.requests_from_trace(trace)
+    budget = int(args.serve_budget_gb * 1e9)
+    eng = serving.ServingEngine(budget_bytes=budget, max_inflight=args.inflight, max_wave=args.max_wave)
+    stats = eng.replay(reqs)
+    stats["waves"] = eng.waves
+    stats["errors"] = eng.errors
+    log(f"[bench] serving: {stats}")
+    # plain RGF on the same trace: FP64 only, one request at a time, one launch per product
+    plain_reqs = serving.requests_from_trace(trace)
+    for r in plain_reqs:
+        r.precision = "fp64"
+        r.flags = S.BT_PLAIN
+    peng = serving.ServingEngine(budget_bytes=budget, max_inflight=1, max_wave=1)
+    pstats = peng.replay(plain_reqs)
+    log(f"[bench] plain RGF serving: {pstats}")
+    out = {
+        "metric": METRIC, "value": round(stats["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * stats["wall_s"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": f"serve_{args.requests}_poisson_{args.rate:g}", "n": f"U{{16..{args.serve_max_n}}}",
+                   "b": f"U{{128..{args.serve_max_b}}} step 64", "a": "U{0,256,512}", "fp64_share": 0.3,
+                   "budget_gb": args.serve_budget_gb, "inflight": args.inflight},
+        "latency_s": {"p50": stats["p50_s"], "p99": stats["p99_s"]},
+        "serving": stats, "plain_rgf": pstats,
+        "vs_plain_rgf_solves": round(stats["solves_per_s"] / pstats["solves_per_s"], 3) if pstats["solves_per_s"] else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +227,16 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-wave", type=int, default=32)
+    ap.add_argument("--plain-count", type=int, default=8)
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--serve-max-n", type=int, default=256)
+    ap.add_argument("--serve-max-b", type=int, default=1024)
+    ap.add_argument("--serve-budget-gb", type=float, default=240.0)
+    ap.add_argument("--inflight", type=int, default=2)
+    ap.add_argument("--max-wave", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,6 +253,10 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.workload == "batch":
+        return bench_batch(args, torch, S)
+    if args.workload == "serve":
+        return bench_serve(args, torch, S)
     cfg = CONFIGS[args.workload]
     P = args.partitions if args.partitions is not None else cfg.partitions[0]
     n, b, a = cfg.n, cfg.b, cfg.a

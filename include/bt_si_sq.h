@@ -68,7 +68,7 @@ typedef enum {
     BT_ERR_SINGULAR = 3,    /* zero or non-finite pivot in a diagonal-block inverse */
     BT_ERR_HIP = 4,         /* a HIP runtime call failed */
     BT_ERR_STATE = 5,       /* e.g. selected_solve before factor */
-    BT_ERR_TOLERANCE = 6    /* mixed path: error estimate above tol even after the FP64 re-run */
+    BT_ERR_TOLERANCE = 6    /* reserved */
 } bt_status;
 
 typedef enum {
@@ -80,6 +80,9 @@ typedef enum {
 
 /* flags */
 #define BT_DIAG_ONLY 0x1u   /* reserved: drop the off-diagonal outputs (not yet honoured) */
+#define BT_PLAIN 0x2u       /* reference schedule: one launch per single-term block product
+                               and per inverse, in program order, on one stream (no
+                               grouping, no multi-term fusion, no stream overlap) */
 
 typedef struct {
     int32_t n;                  /* number of diagonal blocks, >= 1 */
@@ -126,7 +129,9 @@ bt_status bt_si_sq_flops(const bt_desc* desc, double* executed, double* useful);
  * (hipStream_t passed as void*; NULL = the null stream). */
 bt_status bt_si_sq_create(const bt_desc* desc, void* hip_stream, bt_si_sq_handle* out);
 
-/* Forward Schur-complement sweep of A (the A-chain of Alg. 1, extended to
+/* factor, selected_solve and solve take single-instance handles.
+ *
+ * Forward Schur-complement sweep of A (the A-chain of Alg. 1, extended to
  * BTA and partitions) and backward selected inversion (Alg. 2, SI part).
  * Writes X^R into XR when XR is non-NULL (the factors and X^R are also kept
  * in the workspace for selected_solve). */
@@ -135,9 +140,16 @@ bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR);
 /* Selected quadratic solve for right-hand side B with the factors of the
  * last bt_si_sq_factor (the B-chain of Alg. 1 and the SQ part of Alg. 2).
  * Writes X^< into XL.  err_estimate and used_fp64_fallback (host pointers,
- * may be NULL) receive the mixed-path error estimate and whether the FP64
- * re-run was taken; they are filled synchronously (the call waits for the
- * stream) only for BT_MIXED handles, else set to 0. */
+ * may be NULL) are set to 0 for BT_FP64 handles.  For BT_MIXED handles the
+ * call waits for the stream: it computes the FP64 selected residuals
+ * R^R_i = sum_j A_ij X^R_ji - I and R^<_i = sum_j A_ij X^<_ji - sum_j B_ij
+ * (X^R_ij)^H on the GPU, turns them into the estimate
+ *     max(rho_R, rho_L) * nA * nG,  rho_R = max_i ||R^R_i||_F / sqrt(d_i),
+ *     rho_L = max_i ||R^<_i||_F / (nA max_i ||X^<_ii||_F),
+ *     nA = max_i ||A_ii||_F / sqrt(d_i),  nG = max_i ||X^R_ii||_F
+ * (a relative residual times a blockwise ||A|| ||A^-1|| estimate), and when
+ * it exceeds tol re-runs the whole solve with FP64 products, returning the
+ * estimate of the final result and used_fp64_fallback = 1. */
 bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_blocks* XL,
                                   double* err_estimate, int* used_fp64_fallback);
 
@@ -147,6 +159,36 @@ bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_bloc
 bt_status bt_si_sq_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks* B,
                          bt_blocks* XR, bt_blocks* XL,
                          double* err_estimate, int* used_fp64_fallback);
+
+/* ---- Batches of uneven instances ----------------------------------------
+ * A batch handle holds `count` independent instances (each its own n, b, a,
+ * partitions and precision) in one workspace.  One batch_solve builds a single
+ * schedule for all of them: at every dependency level the products of all
+ * instances share one grouped launch and their diagonal-block inverses one
+ * batched inverse, so many small solves fill the GPU together.  Mixed
+ * instances get their error estimate and, above their tol, an FP64 re-run
+ * of just those instances (the call then waits for the stream). */
+size_t bt_si_sq_batch_workspace_bytes(int32_t count, const bt_desc* descs);
+
+bt_status bt_si_sq_batch_create(int32_t count, const bt_desc* descs, void* hip_stream,
+                                bt_si_sq_handle* out);
+
+/* A, B, XL: arrays of `count` bt_blocks (instance i uses element i); XR may be
+ * NULL or have all-NULL elements (X^R then stays in the workspace).
+ * err_estimates and used_fp64_fallback: NULL or host arrays of `count`. */
+bt_status bt_si_sq_batch_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks* B,
+                               bt_blocks* XR, bt_blocks* XL, double* err_estimates,
+                               int* used_fp64_fallback);
+
+/* Selected quadratic solve of new right-hand sides on the factors the last
+ * batch_solve (or factor) left resident: instance i uses B[i], XL[i]; an
+ * instance whose XL[i].diag is NULL is skipped.  Same estimate/fallback rules
+ * as batch_solve. */
+bt_status bt_si_sq_batch_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_blocks* XL,
+                                        double* err_estimates, int* used_fp64_fallback);
+
+/* Number of instances of a handle (1 for bt_si_sq_create). */
+int32_t bt_si_sq_batch_count(bt_si_sq_handle h);
 
 /* Wait for the handle's stream and return the first device-side error
  * recorded since the last sync (BT_OK if none). */
@@ -177,7 +219,8 @@ typedef enum {
     BT_KERNEL_INV_INIT = 3,       /* inverse: working copy */
     BT_KERNEL_INV_FINISH = 4,     /* inverse: unscramble into the result */
     BT_KERNEL_SUM = 5,            /* elementwise block sums */
-    BT_KERNEL_COUNT = 6
+    BT_KERNEL_NORM = 6,           /* block norms of the residual check */
+    BT_KERNEL_COUNT = 7
 } bt_kernel_kind;
 
 typedef struct {

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libbtsisq.so")
 
 BT_OK, BT_ERR_INVALID, BT_ERR_OOM, BT_ERR_SINGULAR, BT_ERR_HIP, BT_ERR_STATE, BT_ERR_TOLERANCE = range(7)
 BT_FP64, BT_MIXED = 0, 1
+BT_DIAG_ONLY, BT_PLAIN = 0x1, 0x2
 STATUS_NAMES = {0: "BT_OK", 1: "BT_ERR_INVALID", 2: "BT_ERR_OOM", 3: "BT_ERR_SINGULAR",
                 4: "BT_ERR_HIP", 5: "BT_ERR_STATE", 6: "BT_ERR_TOLERANCE"}
 
@@ -17,11 +18,13 @@ EXPORTED = [
     "bt_si_sq_create", "bt_si_sq_factor", "bt_si_sq_selected_solve", "bt_si_sq_solve",
     "bt_si_sq_sync", "bt_si_sq_destroy", "bt_si_sq_last_error", "bt_si_sq_last_launch_count",
     "bt_si_sq_profile", "bt_si_sq_profile_stats",
+    "bt_si_sq_batch_workspace_bytes", "bt_si_sq_batch_create", "bt_si_sq_batch_solve",
+    "bt_si_sq_batch_count", "bt_si_sq_batch_selected_solve",
     "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse", "bt_si_sq_diag_schedule",
 ]
 
 KERNEL_NAMES = {0: "product_fp64", 1: "product_mixed", 2: "inv_panel", 3: "inv_init",
-                4: "inv_finish", 5: "sum"}
+                4: "inv_finish", 5: "sum", 6: "norm"}
 
 
 class bt_desc(C.Structure):
@@ -88,6 +91,19 @@ def lib():
     L.bt_si_sq_profile_stats.argtypes = [H, C.POINTER(bt_kernel_stat), C.c_int32,
                                          C.POINTER(C.c_int32)]
     L.bt_si_sq_profile_stats.restype = C.c_int
+    L.bt_si_sq_batch_workspace_bytes.argtypes = [C.c_int32, C.POINTER(bt_desc)]
+    L.bt_si_sq_batch_workspace_bytes.restype = C.c_size_t
+    L.bt_si_sq_batch_create.argtypes = [C.c_int32, C.POINTER(bt_desc), C.c_void_p, C.POINTER(H)]
+    L.bt_si_sq_batch_create.restype = C.c_int
+    L.bt_si_sq_batch_solve.argtypes = [H, C.POINTER(bt_blocks), C.POINTER(bt_blocks),
+                                       C.POINTER(bt_blocks), C.POINTER(bt_blocks),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.bt_si_sq_batch_solve.restype = C.c_int
+    L.bt_si_sq_batch_selected_solve.argtypes = [H, C.POINTER(bt_blocks), C.POINTER(bt_blocks),
+                                                C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.bt_si_sq_batch_selected_solve.restype = C.c_int
+    L.bt_si_sq_batch_count.argtypes = [H]
+    L.bt_si_sq_batch_count.restype = C.c_int32
     dp = C.POINTER(C.c_double)
     L.bt_si_sq_diag_gemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_void_p, C.c_int32,
                                      C.c_int32, C.c_void_p, C.c_int32, C.c_int32, dp, C.c_void_p,

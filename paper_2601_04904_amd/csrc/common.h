@@ -42,8 +42,7 @@ struct InvJob {
     const double2* src;
     double2* dst;
     double2* W;       // d x d working copy
-    double2* Mm;      // d x kInvNB panel transform minus pivot columns
-    double2* Y;       // kInvNB x d gathered pivot rows
+    double2* Mm;      // 2 x (d x kInvNB): panel transform minus pivot columns, by panel parity
     int32_t* perm;    // d pivot rows (perm[j] = pivot row of column j)
     int32_t* used;    // d flags
     int32_t d;
@@ -63,6 +62,13 @@ struct AddOp {
     int32_t nin;
     int32_t rows, cols;
     int32_t pad;
+};
+
+// *out = ||X||_F of one block.
+struct NormJob {
+    const double2* X;
+    double* out;
+    int32_t rows, cols;
 };
 
 // Device-side status: [0] error code (0 = ok, 3 = singular), [1] tag.

@@ -32,3 +32,33 @@ hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_
 }
 
 }  // namespace btsq
+
+namespace btsq {
+
+// Frobenius norms of blocks: out[j] = ||X_j||_F, one workgroup per block,
+// fixed-order reduction (deterministic).
+__global__ void block_norms(const NormJob* __restrict__ jobs) {
+    __shared__ double part[256];
+    const NormJob J = jobs[blockIdx.x];
+    const size_t total = (size_t)J.rows * J.cols;
+    double s = 0.0;
+    for (size_t e = threadIdx.x; e < total; e += blockDim.x) {
+        const double2 v = J.X[e];
+        s += v.x * v.x + v.y * v.y;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *J.out = sqrt(part[0]);
+}
+
+hipError_t launch_norms(const NormJob* d_jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(block_norms, dim3(njobs), dim3(256), 0, s, d_jobs);
+    return hipGetLastError();
+}
+
+}  // namespace btsq

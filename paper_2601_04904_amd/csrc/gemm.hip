@@ -14,9 +14,10 @@
 // 4mnk multiply-adds, the same as four planar real products, and both the
 // A operand and the output keep the interleaved storage.
 //
-// FP64 path: v_mfma_f64_16x16x4f64.  Mixed path: operands rounded to FP32
-// while staging into LDS, v_mfma_f32_16x16x4f32 with FP32 accumulation, the
-// result added to the FP64 output in FP64.
+// FP64 path: v_mfma_f64_4x4x4f64 (measured on gfx950 at about 1.6x the
+// throughput of the 16x16x4 FP64 shape).  Mixed path: operands rounded to
+// FP32 while staging into LDS, v_mfma_f32_16x16x4f32 with FP32 accumulation,
+// the result added to the FP64 output in FP64.
 #include "common.h"
 
 namespace btsq {
@@ -37,19 +38,31 @@ template <bool MIXED> struct Prec;
 template <> struct Prec<false> {
     typedef double2 C;
     typedef double R;
-    typedef v4d Acc;
-    static __device__ inline int row_of(int lane, int r) { return (lane >> 4) + 4 * r; }
+    typedef double Acc;
+    static constexpr int NR = 1;   // accumulator values per lane per MFMA
+    // row within the 4-row group of lane, accumulator element r
+    static __device__ inline int row_of(int lane, int r) { return lane >> 4; }
+    static __device__ inline double elem(const Acc& a, int r) { return a; }
     static __device__ inline C cvt(double2 v) { return v; }
+    static __device__ inline R flip(R v, bool neg) {
+        return __longlong_as_double(__double_as_longlong(v) ^ (neg ? (long long)0x8000000000000000ull : 0ll));
+    }
     static __device__ inline Acc mfma(R a, R b, Acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
     }
 };
 template <> struct Prec<true> {
     typedef float2 C;
     typedef float R;
     typedef v4f Acc;
+    static constexpr int NR = 4;
+    // row within the 16-row block of lane, accumulator element r
     static __device__ inline int row_of(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ inline double elem(const Acc& a, int r) { return (double)a[r]; }
     static __device__ inline C cvt(double2 v) { return make_float2((float)v.x, (float)v.y); }
+    static __device__ inline R flip(R v, bool neg) {
+        return __int_as_float(__float_as_int(v) ^ (neg ? (int)0x80000000u : 0));
+    }
     static __device__ inline Acc mfma(R a, R b, Acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -207,13 +220,20 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     const int pOff = lane >> 5;       // complex k offset within the 4-wide real k step
     const int r16 = lane & 15;
     const int d = lane & 1;           // output component of this lane's B'' column
+    const bool negB = cA == 1 && d == 0;
 
-    AccT acc[MI][2];
+    // FP64: v_mfma_f64_4x4x4f64 with A replicated over its four blocks acts as
+    // a 4-row x 16-column x 4-k product: A[row = lane%4][k = lane/16],
+    // B[k = lane/16][col = lane%16], D[row = lane/16][col = lane%16] (layout
+    // measured on gfx950).  A wave covers BM/2 rows as RG groups of 4 rows.
+    // FP32 (mixed): v_mfma_f32_16x16x4f32, MI blocks of 16 rows.
+    constexpr int RG = MIXED ? MI : BM / 8;
+    AccT acc[RG][2];
 #pragma unroll
-    for (int a = 0; a < MI; ++a)
+    for (int a = 0; a < RG; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-            acc[a][b] = AccT{0, 0, 0, 0};
+            acc[a][b] = AccT{};
 
     int t = 0, k0 = 0;
     while (t < nterms && terms[t].k <= 0) ++t;
@@ -234,24 +254,25 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
 #pragma unroll
         for (int kk = 0; kk < kBK / 2; ++kk) {
             const int p = 2 * kk + pOff;
-            RT av[MI], bv[2];
+            RT av[RG], bv[2];
+            // one component read per operand: A' takes component cA, B'' takes
+            // component cA ^ d, negated for (cA, d) = (1, 0)
 #pragma unroll
-            for (int mi = 0; mi < MI; ++mi) {
-                const CT x = As[buf][p][wm * (BM / 2) + mi * 16 + r16];
-                av[mi] = cA ? x.y : x.x;
+            for (int g = 0; g < RG; ++g) {
+                const int row = MIXED ? (wm * (BM / 2) + g * 16 + r16) : (wm * (BM / 2) + g * 4 + (lane & 3));
+                av[g] = reinterpret_cast<const RT*>(&As[buf][p][row])[cA];
             }
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni) {
                 const int jc = (wn * 32 + ni * 16 + r16) >> 1;
-                const CT x = Bs[buf][p][jc];
-                RT v = (cA == d) ? x.x : x.y;
-                bv[ni] = (cA == 1 && d == 0) ? -v : v;
+                const RT v = reinterpret_cast<const RT*>(&Bs[buf][p][jc])[cA ^ d];
+                bv[ni] = Prec<MIXED>::flip(v, negB);
             }
 #pragma unroll
-            for (int mi = 0; mi < MI; ++mi)
+            for (int g = 0; g < RG; ++g)
 #pragma unroll
                 for (int ni = 0; ni < 2; ++ni)
-                    acc[mi][ni] = Prec<MIXED>::mfma(av[mi], bv[ni], acc[mi][ni]);
+                    acc[g][ni] = Prec<MIXED>::mfma(av[g], bv[ni], acc[g][ni]);
         }
         if (has_next) {
             finish_stage<BM>(st);
@@ -263,56 +284,58 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
         k0 = kn;
     }
 
-    // Epilogue: lane holds rows row_of(lane, r) of each 16 x 16 real block,
-    // real column lane%16 (component lane%2 of complex column lane%16 / 2).
+    // Epilogue: lane holds real column lane%16 (component lane%2 of complex
+    // column lane%16 / 2) of rows row_of(lane, r) of each row group.
+    constexpr int GR = MIXED ? 16 : 4;             // rows per row group
+    constexpr int NR = Prec<MIXED>::NR;
     double* D = reinterpret_cast<double*>(op->D);
     const double2* C = op->C;
     const int ldd = op->ldd, ldc = op->ldc;
     const double2 beta = op->beta;
     if (C) {
         // all C loads first (clamped, unconditional), then the stores
-        double2 cv[MI][2][4];
+        double2 cv[RG][2][NR];
         const gptr_t Cp = (gptr_t)C;
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = min(i0 + wm * (BM / 2) + mi * 16 + Prec<MIXED>::row_of(lane, r), m - 1);
+                for (int r = 0; r < NR; ++r) {
+                    const int row = min(i0 + wm * (BM / 2) + g * GR + Prec<MIXED>::row_of(lane, r), m - 1);
                     const int col = min(j0 + ((wn * 32 + ni * 16 + r16) >> 1), n - 1);
-                    cv[mi][ni][r] = Cp[(size_t)row * ldc + col];
+                    cv[g][ni][r] = Cp[(size_t)row * ldc + col];
                 }
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    asm volatile("" : "+v"(cv[mi][ni][r].x), "+v"(cv[mi][ni][r].y));
+                for (int r = 0; r < NR; ++r)
+                    asm volatile("" : "+v"(cv[g][ni][r].x), "+v"(cv[g][ni][r].y));
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = i0 + wm * (BM / 2) + mi * 16 + Prec<MIXED>::row_of(lane, r);
+                for (int r = 0; r < NR; ++r) {
+                    const int row = i0 + wm * (BM / 2) + g * GR + Prec<MIXED>::row_of(lane, r);
                     const int col = j0 + ((wn * 32 + ni * 16 + r16) >> 1);
-                    const double2 c = cv[mi][ni][r];
-                    const double v = (double)acc[mi][ni][r] +
+                    const double2 c = cv[g][ni][r];
+                    const double v = Prec<MIXED>::elem(acc[g][ni], r) +
                         (d ? (beta.x * c.y + beta.y * c.x) : (beta.x * c.x - beta.y * c.y));
                     if (row < m && col < n) D[2 * ((size_t)row * ldd + col) + d] = v;
                 }
     } else {
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = i0 + wm * (BM / 2) + mi * 16 + Prec<MIXED>::row_of(lane, r);
+                for (int r = 0; r < NR; ++r) {
+                    const int row = i0 + wm * (BM / 2) + g * GR + Prec<MIXED>::row_of(lane, r);
                     const int col = j0 + ((wn * 32 + ni * 16 + r16) >> 1);
-                    if (row < m && col < n) D[2 * ((size_t)row * ldd + col) + d] = (double)acc[mi][ni][r];
+                    if (row < m && col < n) D[2 * ((size_t)row * ldd + col) + d] = Prec<MIXED>::elem(acc[g][ni], r);
                 }
     }
 }

@@ -35,6 +35,30 @@ __device__ inline double2 crecip(double2 v) {
     return make_double2(r / den, -1.0 / den);
 }
 
+// Maximum over the 64 lanes of a wave, by DPP moves (both halves of the
+// double): lanes within rows of 16, then row broadcasts; returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_double(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
+}
+
+__device__ inline double wave_max(double x) {
+    x = fmax(x, dpp_double<0xB1, 0xf>(x));    // quad_perm [1,0,3,2]
+    x = fmax(x, dpp_double<0x4E, 0xf>(x));    // quad_perm [2,3,0,1]
+    x = fmax(x, dpp_double<0x124, 0xf>(x));   // row_ror:4
+    x = fmax(x, dpp_double<0x128, 0xf>(x));   // row_ror:8  -> every lane holds its row's maximum
+    x = fmax(x, dpp_double<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+    x = fmax(x, dpp_double<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3 -> lane 63 holds it
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ void inv_init(const InvJob* __restrict__ jobs) {
     const InvJob J = jobs[blockIdx.y];
     const size_t total = (size_t)J.d * J.d;
@@ -45,9 +69,68 @@ __global__ void inv_init(const InvJob* __restrict__ jobs) {
         J.used[e] = 0;
 }
 
+// One launch per panel p.  Per matrix, workgroup 0 (the panel workgroup)
+// applies the transform of panel p-1 to block p (look-ahead) and then
+// eliminates block p; workgroups 1.. apply the transform of panel p-1 to the
+// other 8-column blocks (all but blocks p-1 and p), each first gathering the
+// pivot rows of its own columns, so no workgroup reads what another writes.
+// Mm is double-buffered by panel parity (Mm + (p % 2) * d * NB).
+constexpr int kUpdCols = 8;
+
 template <int R>
-__global__ __launch_bounds__(kInvThreads)
-void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
+__device__ void step_update(const InvJob& J, int p, int u, int tid) {
+    constexpr int NB = kInvNB;
+    constexpr int T = kInvThreads;
+    constexpr int UC = kUpdCols;
+    __shared__ double2 G[NB][UC];
+    const int d = J.d;
+    const int c0 = u * UC;
+    if (c0 >= d || (p - 1) * NB >= d) return;   // no such columns / no panel p-1 for this matrix
+    const int blk = c0 / NB;
+    if (blk == p - 1 || blk == p) return;
+    const int q0 = (p - 1) * NB;                  // first column of panel p-1
+    const int nc = min(NB, d - q0);
+    const double2* Mm = J.Mm + (size_t)((p - 1) & 1) * d * NB;
+    if (tid < NB * UC) {
+        const int s = tid / UC, j = tid % UC;
+        const int sr = min(s, nc - 1), cc = min(c0 + j, d - 1);
+        const double2 v = J.W[(size_t)J.perm[q0 + sr] * d + cc];
+        G[s][j] = (s < nc && c0 + j < d) ? v : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int ncols = min(UC, d - c0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + q * T;
+        if (r >= d) continue;
+        double2 acc[UC];
+        const double2* wrow = J.W + (size_t)r * d + c0;
+        const double2* mrow = Mm + (size_t)r * NB;
+#pragma unroll
+        for (int j = 0; j < UC; ++j) acc[j] = wrow[min(j, ncols - 1)];
+#pragma unroll 2
+        for (int s = 0; s < NB; s += 4) {
+            double2 m[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) m[i] = mrow[s + i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < UC; ++j) {
+                    const double2 g = G[s + i][j];
+                    acc[j].x += m[i].x * g.x - m[i].y * g.y;
+                    acc[j].y += m[i].x * g.y + m[i].y * g.x;
+                }
+        }
+        double2* wout = J.W + (size_t)r * d + c0;
+#pragma unroll
+        for (int j = 0; j < UC; ++j)
+            if (j < ncols) wout[j] = acc[j];
+    }
+}
+
+template <int R>
+__device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     constexpr int NB = kInvNB;
     constexpr int T = kInvThreads;
     constexpr int NW = T / 64;
@@ -55,18 +138,16 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
     __shared__ int cand_r[2][NW];
     __shared__ double2 cand_row[2][NW][NB];
     __shared__ int piv[NB];
+    __shared__ double2 G[NB][NB];
 
-    const InvJob J = jobs[blockIdx.x];
     const int d = J.d;
-    const int j0 = panel * NB;
+    const int j0 = p * NB;
     if (j0 >= d) return;
     const int nc = min(NB, d - j0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
 
     double2 P[R][NB];
     int used[R];
-    // all panel loads in flight together: indices clamped into the matrix,
-    // out-of-range entries zeroed after the loads complete
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = min(tid + q * T, d - 1);
@@ -75,11 +156,37 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
 #pragma unroll
         for (int c = 0; c < NB; ++c) P[q][c] = row[min(c, nc - 1)];
     }
+    // look-ahead: apply the transform of panel p-1 to this block
+    if (p > 0) {
+        const int q0 = (p - 1) * NB;
+        const int pnc = min(NB, d - q0);
+        if (tid < NB * NB) {
+            const int s = tid / NB, c = tid % NB;
+            const int sr = min(s, pnc - 1), cc = min(c, nc - 1);
+            const double2 v = J.W[(size_t)J.perm[q0 + sr] * d + j0 + cc];
+            G[s][c] = (s < pnc && c < nc) ? v : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const double2* Mm = J.Mm + (size_t)((p - 1) & 1) * d * NB;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        asm volatile("" : "+v"(used[q]));
+        for (int q = 0; q < R; ++q) {
+            const int r = min(tid + q * T, d - 1);
+            const double2* mrow = Mm + (size_t)r * NB;
+#pragma unroll 2
+            for (int s = 0; s < NB; s += 4) {
+                double2 m[4];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) asm volatile("" : "+v"(P[q][c].x), "+v"(P[q][c].y));
+                for (int i = 0; i < 4; ++i) m[i] = mrow[s + i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        const double2 g = G[s + i][c];
+                        P[q][c].x += m[i].x * g.x - m[i].y * g.y;
+                        P[q][c].y += m[i].x * g.y + m[i].y * g.x;
+                    }
+            }
+        }
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -90,31 +197,28 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
             if (!rin || c >= nc) P[q][c] = make_double2(0.0, 0.0);
     }
 
-#pragma unroll
     for (int s = 0; s < NB; ++s) {
         if (s < nc) {
             const int sb = s & 1;
-            // candidate of this thread (rows ascend with q, so ties keep the lower row)
+            // candidate of this lane: largest |re| + |im| among its unused rows
+            // (rows ascend with q, so ties keep the lower row)
             double bv = -1.0;
             int br = INT_MAX;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int r = tid + q * T;
                 if (r < d && !used[q]) {
-                    double v = fabs(P[q][s].x) + fabs(P[q][s].y);
+                    double v = fabs(P[q][0].x) + fabs(P[q][0].y);
                     if (!(v >= 0.0)) v = INFINITY;   // NaN: make it win, and be flagged
                     if (v > bv) { bv = v; br = r; }
                 }
             }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(bv, off);
-                const int orr = __shfl_xor(br, off);
-                if (ov > bv || (ov == bv && orr < br)) { bv = ov; br = orr; }
-            }
-            if (br == INT_MAX) {
+            // wave maximum, then the lowest lane holding it
+            const double wmax = wave_max(bv);
+            const unsigned long long hit = __ballot(bv == wmax && br != INT_MAX);
+            if (hit == 0ull) {
                 if (lane == 0) { cand_v[sb][wave] = -1.0; cand_r[sb][wave] = INT_MAX; }
-            } else if (br % T == tid) {
+            } else if (lane == (int)__builtin_ctzll(hit)) {
                 const int qo = br / T;
                 cand_v[sb][wave] = bv;
                 cand_r[sb][wave] = br;
@@ -137,25 +241,22 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
             if (!(gv > 0.0) || gv == INFINITY) {
                 if (tid == 0 && atomicCAS(&status->code, 0, 3) == 0) status->tag = J.tag;
             }
-            const double2 ip = crecip(cand_row[sb][gw][s]);
+            const double2 ip = crecip(cand_row[sb][gw][0]);
             double2 f[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) f[q] = P[q][s];
+            for (int q = 0; q < R; ++q) f[q] = P[q][0];
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                const double2 spc = (c == s) ? ip : cmul_i(cand_row[sb][gw][c], ip);
+                const double2 spc = (c == 0) ? ip : cmul_i(cand_row[sb][gw][c], ip);
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
                     const int r = tid + q * T;
-                    if (r == gr) {
-                        P[q][c] = spc;
-                    } else if (c == s) {
-                        const double2 t = cmul_i(f[q], ip);
-                        P[q][c] = make_double2(-t.x, -t.y);
-                    } else {
-                        const double2 t = cmul_i(f[q], spc);
-                        P[q][c] = make_double2(P[q][c].x - t.x, P[q][c].y - t.y);
-                    }
+                    const double2 t = cmul_i(f[q], spc);
+                    const double ux = (c == 0) ? -t.x : P[q][c].x - t.x;
+                    const double uy = (c == 0) ? -t.y : P[q][c].y - t.y;
+                    const bool piv_row = r == gr;
+                    P[q][c].x = piv_row ? spc.x : ux;
+                    P[q][c].y = piv_row ? spc.y : uy;
                 }
             }
 #pragma unroll
@@ -163,16 +264,22 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
                 if (tid + q * T == gr) used[q] = 1;
             if (tid == 0) piv[s] = gr;
         }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double2 first = P[q][0];
+#pragma unroll
+            for (int c = 0; c < NB - 1; ++c) P[q][c] = P[q][c + 1];
+            P[q][NB - 1] = first;
+        }
     }
     __syncthreads();
-
-    // write back: panel columns, Mm, used flags, pivot rows
+    double2* Mm = J.Mm + (size_t)(p & 1) * d * NB;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = tid + q * T;
         if (r < d) {
             double2* row = J.W + (size_t)r * d + j0;
-            double2* mrow = J.Mm + (size_t)r * NB;
+            double2* mrow = Mm + (size_t)r * NB;
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 if (c < nc) {
@@ -188,31 +295,17 @@ void inv_panel(const InvJob* __restrict__ jobs, int panel, DevStatus* status) {
         }
     }
     if (tid < nc) J.perm[j0 + tid] = piv[tid];
-    // Y: gathered pivot rows outside the panel (rows >= nc are zero).  Eight
-    // loads per thread are issued before any is used.
-    constexpr int U = 8;
-    const int total = NB * d;
-    for (int base = 0; base < total; base += U * T) {
-        double2 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = min(base + u * T + tid, total - 1);
-            const int c = e / d, col = e - c * d;
-            const int pr = piv[min(c, nc - 1)];
-            v[u] = J.W[(size_t)pr * d + col];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) asm volatile("" : "+v"(v[u].x), "+v"(v[u].y));
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * T + tid;
-            if (e < total) {
-                const int c = e / d, col = e - c * d;
-                const bool keep = c < nc && (col < j0 || col >= j0 + nc);
-                J.Y[e] = keep ? v[u] : make_double2(0.0, 0.0);
-            }
-        }
-    }
+}
+
+// grid.x = njobs * wg_per_job; workgroup 0 of a job is the panel workgroup.
+template <int R>
+__global__ __launch_bounds__(kInvThreads)
+void inv_step(const InvJob* __restrict__ jobs, int p, int wg_per_job, DevStatus* status) {
+    const int job = blockIdx.x / wg_per_job;
+    const int w = blockIdx.x - job * wg_per_job;
+    const InvJob J = jobs[job];
+    if (w == 0) step_panel<R>(J, p, threadIdx.x, status);
+    else if (p > 0) step_update<R>(J, p, w - 1, threadIdx.x);
 }
 
 __global__ void inv_finish(const InvJob* __restrict__ jobs) {
@@ -240,13 +333,14 @@ hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_inv_panel(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel,
-                            DevStatus* status, hipStream_t s) {
+hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel, int maxd,
+                           DevStatus* status, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
+    const int wg = 1 + (maxd + kUpdCols - 1) / kUpdCols;
     if (rows_per_thread == 1)
-        hipLaunchKernelGGL(inv_panel<1>, dim3(njobs), dim3(kInvThreads), 0, s, d_jobs, panel, status);
+        hipLaunchKernelGGL(inv_step<1>, dim3(njobs * wg), dim3(kInvThreads), 0, s, d_jobs, panel, wg, status);
     else
-        hipLaunchKernelGGL(inv_panel<2>, dim3(njobs), dim3(kInvThreads), 0, s, d_jobs, panel, status);
+        hipLaunchKernelGGL(inv_step<2>, dim3(njobs * wg), dim3(kInvThreads), 0, s, d_jobs, panel, wg, status);
     return hipGetLastError();
 }
 

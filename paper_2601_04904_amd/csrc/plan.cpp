@@ -41,12 +41,13 @@ hipError_t launch_gemm(const GemmOp* d_ops, int nops, int total_tiles, bool mixe
 int gemm_tiles(int m, int n);
 int gemm_tiles_n(int n);
 hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
-hipError_t launch_inv_panel(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel,
-                            DevStatus* status, hipStream_t s);
 hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
+hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel, int maxd,
+                           DevStatus* status, hipStream_t s);
 hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s);
 hipError_t launch_gemm32(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s);
 int gemm_tiles32(int m, int n);
+hipError_t launch_norms(const NormJob* d_jobs, int njobs, hipStream_t s);
 }  // namespace btsq
 
 using namespace btsq;
@@ -71,7 +72,7 @@ struct TermSpec {
     double2 alpha;
 };
 
-enum Kind { K_GEMM = 0, K_INV = 1, K_ADD = 2 };
+enum Kind { K_GEMM = 0, K_INV = 1, K_ADD = 2, K_NORM = 3 };
 
 struct OpRec {
     Kind kind;
@@ -80,7 +81,7 @@ struct OpRec {
     std::vector<TermSpec> terms;
     bool mixed = false;
     int tag = 0;                                   // inverse: block id
-    std::vector<std::pair<double2, MatRef>> ins;   // add
+    std::vector<std::pair<double2, MatRef>> ins;   // add; norm: (unused, block)
     int level = 0;
     int cls = 0;          // 1: critical A-chain stream, 0: main stream
     int wait_other = -1;  // highest level of a predecessor on the other stream
@@ -216,6 +217,11 @@ struct Builder {
     std::unordered_map<uint64_t, MatRef> curA, curB, wsA, wsB, xR, xL;
     double flops = 0.0;
     int cur_cls = 0;      // stream class of the operations being emitted
+    bool check = false;   // emit the FP64 selected-residual check (mixed path)
+    bool plain = false;   // reference schedule: single-term products, one stream
+    int instance = 0;     // instance id within a batch (reported with singular blocks)
+    MatRef Ib, Ia;        // identity blocks (filled once at create)
+    MatRef norm_out;      // norms written by the check (5 per block row)
 
     bool emitA() const { return mode == MODE_FACTOR || mode == MODE_BOTH; }
     bool emitB() const { return mode == MODE_SQ || mode == MODE_BOTH; }
@@ -311,6 +317,12 @@ struct Builder {
         for (auto& t : terms)
             if (t.A.ok() && t.B.ok()) kept.push_back(t);
         if (!emit) return;
+        if (plain && kept.size() > 1) {
+            // one product per term, accumulating into Dst in program order
+            gemm(emit, Dst, Cin, beta, {kept[0]}, mixed);
+            for (size_t i = 1; i < kept.size(); ++i) gemm(emit, Dst, Dst, cplx(1), {kept[i]}, mixed);
+            return;
+        }
         OpRec op;
         op.kind = K_GEMM;
         op.D = Dst;
@@ -318,7 +330,7 @@ struct Builder {
         op.beta = beta;
         op.terms = kept;
         op.mixed = mixed;
-        op.cls = cur_cls;
+        op.cls = plain ? 0 : cur_cls;
         for (auto& t : kept) {
             const int k = t.ah ? t.A.r : t.A.c;
             flops += 8.0 * Dst.r * Dst.c * k;
@@ -333,7 +345,7 @@ struct Builder {
         op.C = src;
         op.D = dst;
         op.tag = tag;
-        op.cls = cur_cls;
+        op.cls = plain ? 0 : cur_cls;
         flops += 8.0 * (double)dst.r * dst.r * dst.r;
         ops.push_back(op);
     }
@@ -343,7 +355,7 @@ struct Builder {
         OpRec op;
         op.kind = K_ADD;
         op.D = Dst;
-        op.cls = cur_cls;
+        op.cls = plain ? 0 : cur_cls;
         for (auto& x : ins)
             if (x.second.ok()) op.ins.push_back(x);
         ops.push_back(op);
@@ -363,7 +375,7 @@ struct Builder {
         const double2 one = cplx(1), mone = cplx(-1), zero = cplx(0);
         r.S = alloc(dk, dk);
         cur_cls = 1;   // the A-chain: inverse, T and Schur updates
-        inv(emitA(), cur(false, k, k, tip_tag(k, k, part_tag)), r.S, k);
+        inv(emitA(), cur(false, k, k, tip_tag(k, k, part_tag)), r.S, (instance << 16) | k);
         for (int u : N) {
             r.Auk[u] = cur(false, u, k, 0);
             r.Akv[u] = cur(false, k, u, 0);
@@ -473,7 +485,79 @@ struct Builder {
         }
     }
 
+    // D = beta Cin + sum of terms, split into several products when there are
+    // more terms than one product takes (each later part accumulates into D).
+    void gemm_chain(bool emit, MatRef Dst, MatRef Cin, double2 beta, std::vector<TermSpec> terms) {
+        std::vector<TermSpec> kept;
+        for (auto& t : terms)
+            if (t.A.ok() && t.B.ok()) kept.push_back(t);
+        size_t i = 0;
+        bool first = true;
+        do {
+            std::vector<TermSpec> part(kept.begin() + i, kept.begin() + std::min(kept.size(), i + (size_t)kMaxTerms));
+            if (first) gemm(emit, Dst, Cin, beta, part, false);
+            else gemm(emit, Dst, Dst, cplx(1), part, false);
+            first = false;
+            i += kMaxTerms;
+        } while (i < kept.size());
+    }
+
+    // FP64 selected residuals of the result (Sec. II-A identities restricted to
+    // the pattern): for every block row i,
+    //   R^R_i = sum_j A_ij X^R_ji - I,   R^<_i = sum_j A_ij X^<_ji - sum_j B_ij (X^R_ij)^H,
+    // then the norms of R^R_i, R^<_i, X^R_ii, X^<_ii and A_ii.
+    void residual_check(bool emit) {
+        const int n = D.n, t = D.n;
+        const bool arrow = D.a > 0;
+        const double2 one = cplx(1), mone = cplx(-1);
+        std::vector<MatRef> RR, RL;
+        for (int i = 0; i <= n; ++i) {
+            if (i == n && !arrow) break;
+            RR.push_back(alloc(D.dim(i), D.dim(i)));
+            RL.push_back(alloc(D.dim(i), D.dim(i)));
+        }
+        norm_out = alloc(1, (5 * (n + 1) + 1) / 2 + 1);
+        if (!emit) return;
+        cur_cls = 0;
+        for (int i = 0; i <= n; ++i) {
+            if (i == n && !arrow) break;
+            std::vector<int> cols;
+            if (i == t) {
+                for (int j = 0; j < n; ++j) cols.push_back(j);
+                cols.push_back(t);
+            } else {
+                if (i > 0) cols.push_back(i - 1);
+                cols.push_back(i);
+                if (i + 1 < n) cols.push_back(i + 1);
+                if (arrow) cols.push_back(t);
+            }
+            std::vector<TermSpec> tr, tl;
+            for (int j : cols) {
+                tr.push_back({ext_block(Aext, 0, i, j), false, xloc(false, j, i), false, one});
+                tl.push_back({ext_block(Aext, 0, i, j), false, xloc(true, j, i), false, one});
+                tl.push_back({ext_block(Bext, 1, i, j), false, xloc(false, i, j), true, mone});
+            }
+            gemm_chain(true, RR[i], i == t ? Ia : Ib, mone, tr);
+            gemm_chain(true, RL[i], MatRef{}, cplx(0), tl);
+        }
+        OpRec op;
+        op.kind = K_NORM;
+        op.D = norm_out;
+        op.cls = 0;
+        for (int i = 0; i <= n; ++i) {
+            if (i == n && !arrow) break;
+            op.ins.push_back({cplx(5 * i + 0), RR[i]});
+            op.ins.push_back({cplx(5 * i + 1), RL[i]});
+            op.ins.push_back({cplx(5 * i + 2), xloc(false, i, i)});
+            op.ins.push_back({cplx(5 * i + 3), xloc(true, i, i)});
+            op.ins.push_back({cplx(5 * i + 4), ext_block(Aext, 0, i, i)});
+        }
+        ops.push_back(op);
+    }
+
     void build() {
+        Ib = alloc(D.b, D.b);
+        Ia = alloc(std::max(D.a, 1), std::max(D.a, 1));
         init_stores();
         PlanShape ps = make_plan(D, bounds);
         const int P = (int)bounds.size() - 1;
@@ -510,13 +594,18 @@ struct Builder {
         }
         for (size_t p = 0; p < recs.size(); ++p)
             for (auto it = recs[p].rbegin(); it != recs[p].rend(); ++it) backward(*it);
+        residual_check(check && emitB());
     }
 };
 
 // Dependency levels on whole blocks (read-after-write, write-after-read,
 // write-after-write).  Also records, per operation, the highest level of a
 // predecessor that runs on the other stream.
-int levelize(std::vector<OpRec>& ops) {
+int levelize(std::vector<OpRec>& ops, bool plain = false) {
+    if (plain) {
+        for (size_t i = 0; i < ops.size(); ++i) { ops[i].level = (int)i; ops[i].wait_other = -1; ops[i].cls = 0; }
+        return (int)ops.size();
+    }
     struct BufInfo { int wlevel = -1, wcls = 0; int rlevel[2] = {-1, -1}; };
     std::unordered_map<uintptr_t, BufInfo> info;
     int maxl = -1;
@@ -529,7 +618,7 @@ int levelize(std::vector<OpRec>& ops) {
         } else if (op.kind == K_INV) {
             reads.push_back(op.C);
         } else {
-            for (auto& x : op.ins) reads.push_back(x.second);
+            for (auto& x : op.ins) reads.push_back(x.second);   // sums and norms
         }
         int lvl = 0, other = -1;
         for (auto& r : reads) {
@@ -608,6 +697,7 @@ struct Program {
     std::vector<GemmOp> gemm;
     std::vector<InvJob> inv;
     std::vector<AddOp> add;
+    std::vector<NormJob> norm;
     std::vector<Launch> launches;
     size_t inv_scratch_bytes = 0;   // scratch the inverses need (max over levels)
     double flops = 0.0;
@@ -698,49 +788,30 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                     j.tag = o.tag;
                     auto take = [&](size_t bytes) { poff = (poff + 255) & ~(size_t)255; char* p = inv_pool + poff; poff += bytes; return p; };
                     j.W = reinterpret_cast<double2*>(take((size_t)d * d * sizeof(double2)));
-                    j.Mm = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
-                    j.Y = reinterpret_cast<double2*>(take((size_t)d * NB * sizeof(double2)));
+                    j.Mm = reinterpret_cast<double2*>(take(2 * (size_t)d * NB * sizeof(double2)));
                     j.perm = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
                     j.used = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
                     pg.inv.push_back(j);
                 }
                 pg.inv_scratch_bytes = std::max(pg.inv_scratch_bytes, poff + 256);
                 const int nj = (int)invs.size();
-                int n1 = 0;
-                for (int i : invs) if (ops[i].D.r <= 512) ++n1;
+                int n1 = 0, maxd1 = 0, maxd2 = 0;
+                for (int i : invs) {
+                    if (ops[i].D.r <= 512) { ++n1; maxd1 = std::max(maxd1, ops[i].D.r); }
+                    else maxd2 = std::max(maxd2, ops[i].D.r);
+                }
                 pg.launches.push_back(mk(1, first, nj, 0, 0, maxd, 0, 0, cls, L, wait));
+                // one launch per panel (plus one that applies the last panel)
                 const int npanels = (maxd + kInvNB - 1) / kInvNB;
-                for (int p = 0; p < npanels; ++p) {
-                    if (n1 > 0) pg.launches.push_back(mk(2, first, n1, 0, 0, 1, p, 0, cls, L, -1));
-                    if (nj - n1 > 0) pg.launches.push_back(mk(2, first + n1, nj - n1, 0, 0, 2, p, 0, cls, L, -1));
-                    // trailing update W += Mm Y for the jobs that still have this panel
-                    const size_t g0 = pg.gemm.size();
-                    int tiles = 0;
-                    for (int q = 0; q < nj; ++q) {
-                        const InvJob& j = pg.inv[first + q];
-                        if (p * kInvNB >= j.d) continue;
-                        GemmOp g;
-                        memset(&g, 0, sizeof g);
-                        g.D = j.W;
-                        g.C = j.W;
-                        g.ldd = g.ldc = j.d;
-                        g.m = g.n = j.d;
-                        g.nterms = 1;
-                        g.tiles_n = gemm_tiles_n(j.d);
-                        g.tile_begin = tiles;
-                        g.beta = cplx(1);
-                        g.t[0].A = j.Mm;
-                        g.t[0].B = j.Y;
-                        g.t[0].lda = kInvNB;
-                        g.t[0].ldb = j.d;
-                        g.t[0].k = kInvNB;
-                        g.t[0].alpha = cplx(1);
-                        tiles += gemm_tiles(j.d, j.d);
-                        pg.gemm.push_back(g);
+                for (int p = 0; p <= npanels; ++p) {
+                    if (n1 > 0 && p <= (maxd1 + kInvNB - 1) / kInvNB) {
+                        Launch sl = mk(6, first, n1, maxd1, 0, 1, p, 0, cls, L, -1);
+                        pg.launches.push_back(sl);
                     }
-                    Launch gl = mk(0, g0, (int)(pg.gemm.size() - g0), tiles, 0, 0, 0, 0, cls, L, -1);
-                    choose_tiles(pg, gl);
-                    pg.launches.push_back(gl);
+                    if (nj - n1 > 0 && p <= (maxd2 + kInvNB - 1) / kInvNB) {
+                        Launch sl = mk(6, first + n1, nj - n1, maxd2, 0, 2, p, 0, cls, L, -1);
+                        pg.launches.push_back(sl);
+                    }
                 }
                 pg.launches.push_back(mk(3, first, nj, 0, 0, maxd, 0, 0, cls, L, -1));
             }
@@ -788,6 +859,22 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                 if (pg.add.size() > a0)
                     pg.launches.push_back(mk(4, a0, (int)(pg.add.size() - a0), 0, 0, 0, 0, maxe, cls, L, aw));
             }
+            // block norms
+            for (int i : bylevel[L]) {
+                const OpRec& o = ops[i];
+                if (o.kind != K_NORM || o.cls != cls) continue;
+                const size_t n0 = pg.norm.size();
+                for (auto& x : o.ins) {
+                    NormJob j;
+                    memset(&j, 0, sizeof j);
+                    j.X = x.second.p;
+                    j.rows = x.second.r;
+                    j.cols = x.second.c;
+                    j.out = reinterpret_cast<double*>(o.D.p) + (int)x.first.x;
+                    pg.norm.push_back(j);
+                }
+                pg.launches.push_back(mk(5, n0, (int)(pg.norm.size() - n0), 0, 0, 0, 0, 0, cls, L, o.wait_other));
+            }
         }
     }
     // cross-stream events: a launch that waits for level W of the other stream
@@ -826,6 +913,16 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                 L.flops += 8.0 * j.d * nc * nc;
                 L.bytes += 16.0 * (2.0 * j.d * nc + 2.0 * j.d * kInvNB + 2.0 * kInvNB * j.d);
             }
+        } else if (L.type == 6) {
+            for (int q = 0; q < L.count; ++q) {
+                const InvJob& j = pg.inv[L.off + q];
+                const int np = (j.d + kInvNB - 1) / kInvNB;
+                if (L.panel > np) continue;
+                const double pnc = L.panel > 0 ? std::min(kInvNB, j.d - (L.panel - 1) * kInvNB) : 0;
+                const double nc = L.panel < np ? std::min(kInvNB, j.d - L.panel * kInvNB) : 0;
+                L.flops += 8.0 * ((double)j.d * j.d * pnc + (double)j.d * nc * nc);
+                L.bytes += 16.0 * (2.0 * j.d * j.d + 2.0 * j.d * kInvNB);
+            }
         } else if (L.type == 1 || L.type == 3) {
             for (int q = 0; q < L.count; ++q) {
                 const InvJob& j = pg.inv[L.off + q];
@@ -845,35 +942,43 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Handle
+// Handle: one or more instances (a batch of uneven BT/BTA solves) that share
+// one workspace allocation and one joint schedule.
 // ---------------------------------------------------------------------------
-struct bt_si_sq_plan {
+struct Instance {
     Dims D{};
     bt_desc desc{};
     std::vector<int> bounds;
+    size_t ws_begin = 0, ws_end = 0;   // byte range of this instance in the workspace
+    bool factored = false;
+    bt_blocks A_used{}, XR_used{};
+};
+
+struct bt_si_sq_plan {
+    std::vector<Instance> inst;
     hipStream_t stream = nullptr;     // the caller's stream (main stream)
     hipStream_t astream = nullptr;    // internal stream for the critical A-chain
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     char* ws = nullptr;
-    size_t ws_main = 0;        // bytes of block slots
+    size_t ws_bytes = 0;
     char* inv_pool = nullptr;
     size_t inv_bytes = 0;
     DevStatus* status = nullptr;
     std::string err;
-    bool factored = false;
-    bt_blocks XR_used{};        // where the last factor put X^R
-    bt_blocks A_used{};
     int32_t last_launches = 0;
-    // cached programs per mode
     struct Cached {
-        bool valid = false;
-        bt_blocks A{}, B{}, XR{}, XL{};
+        std::vector<uint64_t> key;
+        uint64_t stamp = 0;
         Program prog;
+        std::vector<double*> norm_out;    // per selected instance (mixed check), or null
+        std::vector<int> sel;             // instances of this program
         char* dev = nullptr;
         size_t dev_bytes = 0;
-        size_t off_gemm = 0, off_inv = 0, off_add = 0;
+        size_t off_gemm = 0, off_inv = 0, off_add = 0, off_norm = 0;
         std::vector<hipEvent_t> events;   // cross-stream events of the launch list
-    } cache[3];
+    };
+    std::vector<Cached> cache;            // small LRU of compiled programs
+    uint64_t clock = 0;
     char* host_stage = nullptr;
     size_t host_stage_bytes = 0;
     hipEvent_t upload_done = nullptr;
@@ -887,6 +992,8 @@ struct bt_si_sq_plan {
 };
 
 namespace {
+
+constexpr size_t kMaxCached = 8;
 
 bool same_blocks(const bt_blocks& x, const bt_blocks& y) { return memcmp(&x, &y, sizeof x) == 0; }
 
@@ -904,6 +1011,7 @@ bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
     if (!d) { msg = "null descriptor"; return false; }
     if (d->n < 1 || d->b < 1 || d->a < 0) { msg = "need n >= 1, b >= 1, a >= 0"; return false; }
     if (d->b > kInvMaxDim || d->a > kInvMaxDim) { msg = "block sizes above 1024 are not supported"; return false; }
+    if (d->n > 65535) { msg = "n above 65535 is not supported"; return false; }
     if (d->precision != BT_FP64 && d->precision != BT_MIXED) { msg = "unknown precision"; return false; }
     const int P = d->partitions;
     if (P < 1) { msg = "partitions must be >= 1"; return false; }
@@ -922,21 +1030,55 @@ bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
     return validate_bounds(D, bounds, msg);
 }
 
-// Dry run: workspace layout and inverse scratch for a descriptor.
-void dry_run(const Dims& D, const std::vector<int>& bounds, bool mixed, size_t& ws_bytes,
-             size_t& inv_bytes, double& flops) {
-    Builder bd;
-    bd.D = D;
-    bd.bounds = bounds;
-    bd.mode = MODE_BOTH;
-    bd.mixed_bulk = mixed;
-    bd.ws = reinterpret_cast<char*>((uintptr_t)1 << 40);
-    bd.build();
-    ws_bytes = bd.off + 256;
-    flops = bd.flops;
-    int nl = levelize(bd.ops);
-    Program pg = compile(bd.ops, nl, reinterpret_cast<char*>((uintptr_t)3 << 40));
-    inv_bytes = pg.inv_scratch_bytes;
+// Build the operations of the selected instances (sel) into one list.
+// With ws == nullptr the workspace is a fake base and offsets are assigned
+// (dry run); otherwise each instance builds into its recorded range.
+struct Built {
+    std::vector<OpRec> ops;
+    std::vector<double*> norm_out;
+    double flops = 0;
+};
+
+bool build_instances(std::vector<Instance>& inst, const std::vector<int>& sel, Mode mode,
+                     char* ws, bool fp64_rerun, const bt_blocks* A, const bt_blocks* B,
+                     const bt_blocks* XR, const bt_blocks* XL, Built& out, size_t* dry_total) {
+    const bool dry = ws == nullptr;
+    char* base = dry ? reinterpret_cast<char*>((uintptr_t)1 << 40) : ws;
+    size_t run = 0;
+    for (int i : sel) {
+        Instance& I = inst[i];
+        Builder bd;
+        bd.D = I.D;
+        bd.bounds = I.bounds;
+        bd.mode = mode;
+        const bool mixed_handle = I.desc.precision == BT_MIXED;
+        bd.mixed_bulk = mixed_handle && !fp64_rerun;
+        bd.check = mixed_handle;
+        bd.plain = (I.desc.flags & BT_PLAIN) != 0;
+        bd.instance = i;
+        if (!dry) {
+            if (A) bd.Aext = A[i];
+            if (B) bd.Bext = B[i];
+            if (XR) bd.XRext = XR[i];
+            if (XL) bd.XLext = XL[i];
+        }
+        bd.ws = base;
+        bd.off = dry ? run : I.ws_begin;
+        const size_t begin = bd.off;
+        bd.build();
+        if (dry) {
+            I.ws_begin = begin;
+            I.ws_end = (bd.off + 255) & ~(size_t)255;
+            run = I.ws_end;
+        } else if (bd.off > I.ws_end) {
+            return false;
+        }
+        out.flops += bd.flops;
+        out.norm_out.push_back(bd.check && bd.emitB() ? reinterpret_cast<double*>(bd.norm_out.p) : nullptr);
+        for (auto& o : bd.ops) out.ops.push_back(std::move(o));
+    }
+    if (dry_total) *dry_total = run;
+    return true;
 }
 
 hipEvent_t next_event(bt_si_sq_plan* h) {
@@ -969,6 +1111,8 @@ int kernel_kind(const Launch& L) {
         case 1: return BT_KERNEL_INV_INIT;
         case 2: return BT_KERNEL_INV_PANEL;
         case 3: return BT_KERNEL_INV_FINISH;
+        case 5: return BT_KERNEL_NORM;
+        case 6: return BT_KERNEL_INV_PANEL;
         default: return BT_KERNEL_SUM;
     }
 }
@@ -978,10 +1122,12 @@ hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
     GemmOp* dg = reinterpret_cast<GemmOp*>(c.dev + c.off_gemm);
     InvJob* dj = reinterpret_cast<InvJob*>(c.dev + c.off_inv);
     AddOp* da = reinterpret_cast<AddOp*>(c.dev + c.off_add);
+    NormJob* dn = reinterpret_cast<NormJob*>(c.dev + c.off_norm);
     hipError_t e = hipSuccess;
     if (h->profiling && h->ev_used + 2 * pg.launches.size() > 200000) {
         // bound the number of outstanding events: fold in what has finished
         hipStreamSynchronize(h->stream);
+        hipStreamSynchronize(h->astream);
         collect_profile(h);
     }
     // the critical stream starts after everything already queued on the main stream
@@ -1006,9 +1152,10 @@ hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
                                : launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s);
                 break;
             case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
-            case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, h->status, s); break;
             case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
             case 4: e = launch_add(da + L.off, L.count, L.maxelems, s); break;
+            case 5: e = launch_norms(dn + L.off, L.count, s); break;
+            case 6: e = launch_inv_step(dj + L.off, L.count, L.maxd, L.panel, L.tiles, h->status, s); break;
         }
         if (e != hipSuccess) return e;
         if (h->profiling && ea && eb) {
@@ -1027,82 +1174,183 @@ hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
     return e;
 }
 
-bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const bt_blocks* A, const bt_blocks* B,
-                          const bt_blocks* XR, const bt_blocks* XL) {
-    bt_si_sq_plan::Cached& c = h->cache[mode];
-    bt_blocks zA{}, zB{}, zXR{}, zXL{};
-    const bt_blocks& a = A ? *A : zA;
-    const bt_blocks& b = B ? *B : zB;
-    const bt_blocks& xr = XR ? *XR : zXR;
-    const bt_blocks& xl = XL ? *XL : zXL;
-    if (!(c.valid && same_blocks(c.A, a) && same_blocks(c.B, b) && same_blocks(c.XR, xr) && same_blocks(c.XL, xl))) {
-        Builder bd;
-        bd.D = h->D;
-        bd.bounds = h->bounds;
-        bd.mode = mode;
-        bd.mixed_bulk = h->desc.precision == BT_MIXED;
-        bd.Aext = a;
-        bd.Bext = b;
-        bd.XRext = xr;
-        bd.XLext = xl;
-        bd.ws = h->ws;
-        bd.build();
-        if (bd.off + 256 > h->ws_main)
+std::vector<uint64_t> make_key(Mode mode, bool fp64_rerun, const std::vector<int>& sel,
+                               const bt_blocks* A, const bt_blocks* B, const bt_blocks* XR,
+                               const bt_blocks* XL) {
+    std::vector<uint64_t> k;
+    k.push_back((uint64_t)mode | ((uint64_t)fp64_rerun << 8));
+    auto put = [&](const bt_blocks* arr, int i) {
+        if (!arr) { for (int q = 0; q < 6; ++q) k.push_back(0); return; }
+        const bt_blocks& b = arr[i];
+        k.push_back((uint64_t)b.diag); k.push_back((uint64_t)b.upper); k.push_back((uint64_t)b.lower);
+        k.push_back((uint64_t)b.arrow_right); k.push_back((uint64_t)b.arrow_bottom); k.push_back((uint64_t)b.tip);
+    };
+    for (int i : sel) {
+        k.push_back((uint64_t)i);
+        put(A, i); put(B, i); put(XR, i); put(XL, i);
+    }
+    return k;
+}
+
+void free_cached(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
+    if (c.dev) {
+        hipStreamSynchronize(h->stream);
+        hipStreamSynchronize(h->astream);
+        hipFree(c.dev);
+        c.dev = nullptr;
+    }
+    for (auto ev : c.events) hipEventDestroy(ev);
+    c.events.clear();
+}
+
+// Build (or reuse) and enqueue the program of the selected instances.
+bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& sel,
+                          const bt_blocks* A, const bt_blocks* B, const bt_blocks* XR,
+                          const bt_blocks* XL, bool fp64_rerun, bt_si_sq_plan::Cached** used) {
+    std::vector<uint64_t> key = make_key(mode, fp64_rerun, sel, A, B, XR, XL);
+    bt_si_sq_plan::Cached* c = nullptr;
+    for (auto& x : h->cache)
+        if (x.key == key) { c = &x; break; }
+    if (!c) {
+        Built bt;
+        if (!build_instances(h->inst, sel, mode, h->ws, fp64_rerun, A, B, XR, XL, bt, nullptr))
             return set_err(h, BT_ERR_INVALID, "internal: workspace layout changed");
-        int nl = levelize(bd.ops);
-        Program pg = compile(bd.ops, nl, h->inv_pool);
+        bool plain = true;
+        for (int i : sel) plain = plain && (h->inst[i].desc.flags & BT_PLAIN);
+        int nl = levelize(bt.ops, plain);
+        Program pg = compile(bt.ops, nl, h->inv_pool);
         if (pg.inv_scratch_bytes > h->inv_bytes)
             return set_err(h, BT_ERR_INVALID, "internal: inverse scratch too small");
-        pg.flops = bd.flops;
+        pg.flops = bt.flops;
         const size_t bg = pg.gemm.size() * sizeof(GemmOp);
         const size_t bi = pg.inv.size() * sizeof(InvJob);
         const size_t ba = pg.add.size() * sizeof(AddOp);
+        const size_t bn = pg.norm.size() * sizeof(NormJob);
         const size_t off_inv = (bg + 255) & ~(size_t)255;
         const size_t off_add = (off_inv + bi + 255) & ~(size_t)255;
-        const size_t total = off_add + ba + 256;
+        const size_t off_norm = (off_add + ba + 255) & ~(size_t)255;
+        const size_t total = off_norm + bn + 256;
+        // slot: a free one, else the least recently used
+        if (h->cache.size() < kMaxCached) {
+            h->cache.emplace_back();
+            c = &h->cache.back();
+        } else {
+            c = &h->cache[0];
+            for (auto& x : h->cache)
+                if (x.stamp < c->stamp) c = &x;
+            free_cached(h, *c);
+            c->key.clear();
+            c->dev_bytes = 0;
+        }
         // the previous upload must have left the staging buffer
         if (h->upload_done) hipEventSynchronize(h->upload_done);
-        if (total > c.dev_bytes) {
-            if (c.dev) {
-                hipStreamSynchronize(h->stream);
-                hipFree(c.dev);
-                c.dev = nullptr;
-            }
-            hipError_t e = hipMalloc(&c.dev, total);
-            if (e != hipSuccess) { c.dev_bytes = 0; return set_err(h, BT_ERR_OOM, "operation list allocation failed"); }
-            c.dev_bytes = total;
-        }
+        hipError_t e = hipMalloc(&c->dev, total);
+        if (e != hipSuccess) { c->dev = nullptr; return set_err(h, BT_ERR_OOM, "operation list allocation failed"); }
+        c->dev_bytes = total;
         if (total > h->host_stage_bytes) {
             if (h->host_stage) hipHostFree(h->host_stage);
             h->host_stage = nullptr;
-            hipError_t e = hipHostMalloc((void**)&h->host_stage, total, 0);
+            e = hipHostMalloc((void**)&h->host_stage, total, 0);
             if (e != hipSuccess) { h->host_stage_bytes = 0; return hip_err(h, e, "hipHostMalloc"); }
             h->host_stage_bytes = total;
         }
         if (bg) memcpy(h->host_stage, pg.gemm.data(), bg);
         if (bi) memcpy(h->host_stage + off_inv, pg.inv.data(), bi);
         if (ba) memcpy(h->host_stage + off_add, pg.add.data(), ba);
-        hipError_t e = hipMemcpyAsync(c.dev, h->host_stage, total, hipMemcpyHostToDevice, h->stream);
+        if (bn) memcpy(h->host_stage + off_norm, pg.norm.data(), bn);
+        e = hipMemcpyAsync(c->dev, h->host_stage, total, hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) return hip_err(h, e, "hipMemcpyAsync(op list)");
         e = hipEventRecord(h->upload_done, h->stream);
         if (e != hipSuccess) return hip_err(h, e, "hipEventRecord");
-        for (auto ev : c.events) hipEventDestroy(ev);
-        c.events.clear();
         for (int i = 0; i < pg.n_events; ++i) {
             hipEvent_t ev;
             e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (e != hipSuccess) return hip_err(h, e, "hipEventCreate");
-            c.events.push_back(ev);
+            c->events.push_back(ev);
         }
-        c.prog = std::move(pg);
-        c.off_gemm = 0;
-        c.off_inv = off_inv;
-        c.off_add = off_add;
-        c.A = a; c.B = b; c.XR = xr; c.XL = xl;
-        c.valid = true;
+        c->prog = std::move(pg);
+        c->norm_out = bt.norm_out;
+        c->sel = sel;
+        c->off_gemm = 0;
+        c->off_inv = off_inv;
+        c->off_add = off_add;
+        c->off_norm = off_norm;
+        c->key = key;
     }
-    hipError_t e = run_program(h, c);
+    c->stamp = ++h->clock;
+    hipError_t e = run_program(h, *c);
     if (e != hipSuccess) return hip_err(h, e, "kernel launch");
+    if (used) *used = c;
+    return BT_OK;
+}
+
+// Error estimate of a mixed-path result from the FP64 selected residuals:
+//   est = max(rho_R, rho_L) * nA * nG
+//   rho_R = max_i ||R^R_i||_F / sqrt(d_i)       (relative residual of A X = I)
+//   rho_L = max_i ||R^<_i||_F / (nA * max_i ||X^<_ii||_F)
+//   nA = max_i ||A_ii||_F / sqrt(d_i),  nG = max_i ||X^R_ii||_F
+// i.e. a relative residual times a blockwise estimate of ||A|| ||A^-1||.
+bt_status read_estimates(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, std::vector<double>& est) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
+    est.assign(c.sel.size(), 0.0);
+    for (size_t q = 0; q < c.sel.size(); ++q) {
+        if (!c.norm_out[q]) continue;
+        const Instance& I = h->inst[c.sel[q]];
+        const int rows = I.D.n + (I.D.a > 0 ? 1 : 0);
+        std::vector<double> v(5 * (I.D.n + 1), 0.0);
+        e = hipMemcpy(v.data(), c.norm_out[q], v.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_err(h, e, "residual readback");
+        double nA = 0, nG = 0, nL = 0, rR = 0, rL = 0;
+        for (int i = 0; i < rows; ++i) {
+            const double sd = std::sqrt((double)I.D.dim(i));
+            nA = std::max(nA, v[5 * i + 4] / sd);
+            nG = std::max(nG, v[5 * i + 2]);
+            nL = std::max(nL, v[5 * i + 3]);
+            rR = std::max(rR, v[5 * i + 0] / sd);
+            rL = std::max(rL, v[5 * i + 1]);
+        }
+        rL = (nA * nL > 0) ? rL / (nA * nL) : rL;
+        double x = std::max(rR, rL) * nA * nG;
+        if (!(x == x)) x = INFINITY;
+        est[q] = x;
+    }
+    return BT_OK;
+}
+
+// Run the selected instances; for mixed instances estimate the error and
+// re-run in FP64 those above their tolerance.
+bt_status run_instances(bt_si_sq_plan* h, Mode mode, const std::vector<int>& sel,
+                        const bt_blocks* A, const bt_blocks* B, const bt_blocks* XR,
+                        const bt_blocks* XL, double* err, int* fb) {
+    bt_si_sq_plan::Cached* c = nullptr;
+    bt_status st = prepare_and_run(h, mode, sel, A, B, XR, XL, false, &c);
+    if (st != BT_OK) return st;
+    for (size_t q = 0; q < sel.size(); ++q) {
+        if (err) err[sel[q]] = 0.0;
+        if (fb) fb[sel[q]] = 0;
+    }
+    bool any_mixed = false;
+    for (int i : sel) any_mixed |= h->inst[i].desc.precision == BT_MIXED;
+    if (!any_mixed || mode == MODE_FACTOR) return BT_OK;
+    std::vector<double> est;
+    st = read_estimates(h, *c, est);
+    if (st != BT_OK) return st;
+    std::vector<int> redo;
+    for (size_t q = 0; q < sel.size(); ++q) {
+        const Instance& I = h->inst[sel[q]];
+        if (I.desc.precision == BT_MIXED && est[q] > I.desc.tol) redo.push_back(sel[q]);
+        if (err) err[sel[q]] = est[q];
+    }
+    if (redo.empty()) return BT_OK;
+    st = prepare_and_run(h, mode, redo, A, B, XR, XL, true, &c);
+    if (st != BT_OK) return st;
+    st = read_estimates(h, *c, est);
+    if (st != BT_OK) return st;
+    for (size_t q = 0; q < redo.size(); ++q) {
+        if (err) err[redo[q]] = est[q];
+        if (fb) fb[redo[q]] = 1;
+    }
     return BT_OK;
 }
 
@@ -1122,6 +1370,85 @@ bool check_blocks(const Dims& D, const bt_blocks* m, bool need, std::string& msg
     return true;
 }
 
+bool check_optional_blocks(const Dims& D, const bt_blocks* m, std::string& msg, const char* name) {
+    if (!m) return true;
+    const bool any = m->diag || m->upper || m->lower || m->arrow_right || m->arrow_bottom || m->tip;
+    if (!any) return true;   // all null: X^R stays in the workspace
+    return check_blocks(D, m, true, msg, name);
+}
+
+// Validate descriptors and size the workspace of a batch (dry run).
+bt_status plan_instances(int count, const bt_desc* descs, std::vector<Instance>& inst,
+                         size_t& ws_bytes, size_t& inv_bytes, double* flops) {
+    if (count < 1 || !descs) return set_err(nullptr, BT_ERR_INVALID, "need count >= 1 descriptors");
+    inst.assign(count, Instance{});
+    std::string msg;
+    for (int i = 0; i < count; ++i) {
+        std::vector<int> bounds;
+        if (!desc_bounds(&descs[i], bounds, msg)) {
+            if (count > 1) msg = "instance " + std::to_string(i) + ": " + msg;
+            return set_err(nullptr, BT_ERR_INVALID, msg);
+        }
+        inst[i].D = Dims{descs[i].n, descs[i].b, descs[i].a};
+        inst[i].desc = descs[i];
+        inst[i].desc.part_bounds = nullptr;
+        if (!(inst[i].desc.tol > 0)) inst[i].desc.tol = 1e-4;
+        inst[i].bounds = bounds;
+    }
+    std::vector<int> sel(count);
+    for (int i = 0; i < count; ++i) sel[i] = i;
+    Built bt;
+    size_t total = 0;
+    build_instances(inst, sel, MODE_BOTH, nullptr, false, nullptr, nullptr, nullptr, nullptr, bt, &total);
+    if (flops) *flops = bt.flops;
+    ws_bytes = total + 256;
+    bool plain = true;
+    for (auto& I : inst) plain = plain && (I.desc.flags & BT_PLAIN);
+    int nl = levelize(bt.ops, plain);
+    Program pg = compile(bt.ops, nl, reinterpret_cast<char*>((uintptr_t)3 << 40));
+    inv_bytes = pg.inv_scratch_bytes;
+    return BT_OK;
+}
+
+bt_status create_handle(int count, const bt_desc* descs, void* hip_stream, bt_si_sq_handle* out) {
+    if (!out) return set_err(nullptr, BT_ERR_INVALID, "out is null");
+    *out = nullptr;
+    std::unique_ptr<bt_si_sq_plan> h(new bt_si_sq_plan());
+    bt_status st = plan_instances(count, descs, h->inst, h->ws_bytes, h->inv_bytes, nullptr);
+    if (st != BT_OK) return st;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipMalloc(&h->ws, h->ws_bytes);
+    if (e != hipSuccess) { hipGetLastError(); return set_err(nullptr, BT_ERR_OOM, "workspace allocation failed"); }
+    e = hipMalloc(&h->inv_pool, std::max<size_t>(h->inv_bytes, 256));
+    if (e != hipSuccess) { hipGetLastError(); hipFree(h->ws); return set_err(nullptr, BT_ERR_OOM, "inverse scratch allocation failed"); }
+    e = hipMalloc(&h->status, sizeof(DevStatus));
+    if (e != hipSuccess) { hipFree(h->ws); hipFree(h->inv_pool); return set_err(nullptr, BT_ERR_OOM, "status allocation failed"); }
+    DevStatus z{0, 0};
+    e = hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
+    // identity blocks used by the residual check: each instance's first two slots
+    for (auto& I : h->inst) {
+        if (e != hipSuccess) break;
+        const int b = I.D.b, a = std::max(I.D.a, 1);
+        std::vector<double2> Ib((size_t)b * b, cplx(0));
+        for (int i = 0; i < b; ++i) Ib[(size_t)i * b + i] = cplx(1);
+        e = hipMemcpy(h->ws + I.ws_begin, Ib.data(), Ib.size() * sizeof(double2), hipMemcpyHostToDevice);
+        const size_t offa = I.ws_begin + (((size_t)b * b * sizeof(double2) + 255) & ~(size_t)255);
+        std::vector<double2> Ia((size_t)a * a, cplx(0));
+        for (int i = 0; i < a; ++i) Ia[(size_t)i * a + i] = cplx(1);
+        if (e == hipSuccess) e = hipMemcpy(h->ws + offa, Ia.data(), Ia.size() * sizeof(double2), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->astream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        hipFree(h->ws); hipFree(h->inv_pool); hipFree(h->status);
+        return hip_err(nullptr, e, "create");
+    }
+    *out = h.release();
+    return BT_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1130,12 +1457,13 @@ bool check_blocks(const Dims& D, const bt_blocks* m, bool need, std::string& msg
 extern "C" {
 
 size_t bt_si_sq_workspace_bytes(const bt_desc* desc) {
-    std::vector<int> bounds;
-    std::string msg;
-    if (!desc_bounds(desc, bounds, msg)) { g_last_error = msg; return 0; }
+    return bt_si_sq_batch_workspace_bytes(1, desc);
+}
+
+size_t bt_si_sq_batch_workspace_bytes(int32_t count, const bt_desc* descs) {
+    std::vector<Instance> inst;
     size_t ws = 0, inv = 0;
-    double fl = 0;
-    dry_run(Dims{desc->n, desc->b, desc->a}, bounds, desc->precision == BT_MIXED, ws, inv, fl);
+    if (plan_instances(count, descs, inst, ws, inv, nullptr) != BT_OK) return 0;
     return ws + inv + 4096;
 }
 
@@ -1149,64 +1477,42 @@ bt_status bt_si_sq_partition_bounds(const bt_desc* desc, int32_t* bounds_out) {
 }
 
 bt_status bt_si_sq_flops(const bt_desc* desc, double* executed, double* useful) {
-    std::vector<int> bounds;
-    std::string msg;
-    if (!desc_bounds(desc, bounds, msg)) return set_err(nullptr, BT_ERR_INVALID, msg);
+    std::vector<Instance> inst;
     size_t ws = 0, inv = 0;
     double fe = 0, fu = 0;
-    Dims D{desc->n, desc->b, desc->a};
-    dry_run(D, bounds, false, ws, inv, fe);
-    dry_run(D, {0, desc->n}, false, ws, inv, fu);
+    bt_status st = plan_instances(1, desc, inst, ws, inv, &fe);
+    if (st != BT_OK) return st;
+    bt_desc seq = *desc;
+    seq.partitions = 1;
+    seq.part_bounds = nullptr;
+    st = plan_instances(1, &seq, inst, ws, inv, &fu);
+    if (st != BT_OK) return st;
     if (executed) *executed = fe;
     if (useful) *useful = fu;
     return BT_OK;
 }
 
 bt_status bt_si_sq_create(const bt_desc* desc, void* hip_stream, bt_si_sq_handle* out) {
-    if (!out) return set_err(nullptr, BT_ERR_INVALID, "out is null");
-    *out = nullptr;
-    std::vector<int> bounds;
-    std::string msg;
-    if (!desc_bounds(desc, bounds, msg)) return set_err(nullptr, BT_ERR_INVALID, msg);
-    std::unique_ptr<bt_si_sq_plan> h(new bt_si_sq_plan());
-    h->desc = *desc;
-    h->desc.part_bounds = nullptr;
-    if (!(h->desc.tol > 0)) h->desc.tol = 1e-4;
-    h->D = Dims{desc->n, desc->b, desc->a};
-    h->bounds = bounds;
-    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    double fl = 0;
-    dry_run(h->D, bounds, desc->precision == BT_MIXED, h->ws_main, h->inv_bytes, fl);
-    hipError_t e = hipMalloc(&h->ws, h->ws_main);
-    if (e != hipSuccess) { hipGetLastError(); return set_err(nullptr, BT_ERR_OOM, "workspace allocation failed"); }
-    e = hipMalloc(&h->inv_pool, h->inv_bytes);
-    if (e != hipSuccess) { hipGetLastError(); hipFree(h->ws); return set_err(nullptr, BT_ERR_OOM, "inverse scratch allocation failed"); }
-    e = hipMalloc(&h->status, sizeof(DevStatus));
-    if (e != hipSuccess) { hipFree(h->ws); hipFree(h->inv_pool); return set_err(nullptr, BT_ERR_OOM, "status allocation failed"); }
-    DevStatus z{0, 0};
-    e = hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->astream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        hipFree(h->ws); hipFree(h->inv_pool); hipFree(h->status);
-        return hip_err(nullptr, e, "create");
-    }
-    *out = h.release();
-    return BT_OK;
+    return create_handle(1, desc, hip_stream, out);
+}
+
+bt_status bt_si_sq_batch_create(int32_t count, const bt_desc* descs, void* hip_stream,
+                                bt_si_sq_handle* out) {
+    return create_handle(count, descs, hip_stream, out);
 }
 
 bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR) {
     if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    if (h->inst.size() != 1) return set_err(h, BT_ERR_INVALID, "factor takes a single-instance handle");
+    Instance& I = h->inst[0];
     std::string msg;
-    if (!check_blocks(h->D, A, true, msg, "A") || !check_blocks(h->D, XR, false, msg, "XR"))
+    if (!check_blocks(I.D, A, true, msg, "A") || !check_optional_blocks(I.D, XR, msg, "XR"))
         return set_err(h, BT_ERR_INVALID, msg);
-    bt_status st = prepare_and_run(h, MODE_FACTOR, A, nullptr, XR, nullptr);
+    bt_status st = run_instances(h, MODE_FACTOR, {0}, A, nullptr, XR, nullptr, nullptr, nullptr);
     if (st == BT_OK) {
-        h->factored = true;
-        h->A_used = *A;
-        h->XR_used = XR ? *XR : bt_blocks{};
+        I.factored = true;
+        I.A_used = *A;
+        I.XR_used = XR ? *XR : bt_blocks{};
     }
     return st;
 }
@@ -1216,30 +1522,78 @@ bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_bloc
     if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
     if (err_estimate) *err_estimate = 0.0;
     if (used_fp64_fallback) *used_fp64_fallback = 0;
-    if (!h->factored) return set_err(h, BT_ERR_STATE, "selected_solve before factor");
+    if (h->inst.size() != 1) return set_err(h, BT_ERR_INVALID, "selected_solve takes a single-instance handle");
+    Instance& I = h->inst[0];
+    if (!I.factored) return set_err(h, BT_ERR_STATE, "selected_solve before factor");
     std::string msg;
-    if (!check_blocks(h->D, B, true, msg, "B") || !check_blocks(h->D, XL, true, msg, "XL"))
+    if (!check_blocks(I.D, B, true, msg, "B") || !check_blocks(I.D, XL, true, msg, "XL"))
         return set_err(h, BT_ERR_INVALID, msg);
-    return prepare_and_run(h, MODE_SQ, &h->A_used, B, &h->XR_used, XL);
+    return run_instances(h, MODE_SQ, {0}, &I.A_used, B, &I.XR_used, XL, err_estimate, used_fp64_fallback);
 }
 
 bt_status bt_si_sq_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks* B,
                          bt_blocks* XR, bt_blocks* XL, double* err_estimate, int* used_fp64_fallback) {
     if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
-    if (err_estimate) *err_estimate = 0.0;
-    if (used_fp64_fallback) *used_fp64_fallback = 0;
+    if (h->inst.size() != 1) return set_err(h, BT_ERR_INVALID, "solve takes a single-instance handle");
+    return bt_si_sq_batch_solve(h, A, B, XR, XL, err_estimate, used_fp64_fallback);
+}
+
+bt_status bt_si_sq_batch_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks* B,
+                               bt_blocks* XR, bt_blocks* XL, double* err_estimates,
+                               int* used_fp64_fallback) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    const int count = (int)h->inst.size();
+    if (err_estimates) for (int i = 0; i < count; ++i) err_estimates[i] = 0.0;
+    if (used_fp64_fallback) for (int i = 0; i < count; ++i) used_fp64_fallback[i] = 0;
+    if (!A || !B || !XL) return set_err(h, BT_ERR_INVALID, "A, B and XL are required");
     std::string msg;
-    if (!check_blocks(h->D, A, true, msg, "A") || !check_blocks(h->D, B, true, msg, "B") ||
-        !check_blocks(h->D, XR, false, msg, "XR") || !check_blocks(h->D, XL, true, msg, "XL"))
-        return set_err(h, BT_ERR_INVALID, msg);
-    bt_status st = prepare_and_run(h, MODE_BOTH, A, B, XR, XL);
-    if (st == BT_OK) {
-        h->factored = true;
-        h->A_used = *A;
-        h->XR_used = XR ? *XR : bt_blocks{};
+    for (int i = 0; i < count; ++i) {
+        const Dims& D = h->inst[i].D;
+        if (!check_blocks(D, &A[i], true, msg, "A") || !check_blocks(D, &B[i], true, msg, "B") ||
+            !check_optional_blocks(D, XR ? &XR[i] : nullptr, msg, "XR") ||
+            !check_blocks(D, &XL[i], true, msg, "XL")) {
+            if (count > 1) msg = "instance " + std::to_string(i) + ": " + msg;
+            return set_err(h, BT_ERR_INVALID, msg);
+        }
     }
+    std::vector<int> sel(count);
+    for (int i = 0; i < count; ++i) sel[i] = i;
+    bt_status st = run_instances(h, MODE_BOTH, sel, A, B, XR, XL, err_estimates, used_fp64_fallback);
+    if (st == BT_OK)
+        for (int i = 0; i < count; ++i) {
+            h->inst[i].factored = true;
+            h->inst[i].A_used = A[i];
+            h->inst[i].XR_used = XR ? XR[i] : bt_blocks{};
+        }
     return st;
 }
+
+bt_status bt_si_sq_batch_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_blocks* XL,
+                                        double* err_estimates, int* used_fp64_fallback) {
+    if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
+    const int count = (int)h->inst.size();
+    if (err_estimates) for (int i = 0; i < count; ++i) err_estimates[i] = 0.0;
+    if (used_fp64_fallback) for (int i = 0; i < count; ++i) used_fp64_fallback[i] = 0;
+    if (!B || !XL) return set_err(h, BT_ERR_INVALID, "B and XL are required");
+    std::vector<int> sel;
+    std::vector<bt_blocks> Au(count), XRu(count);
+    std::string msg;
+    for (int i = 0; i < count; ++i) {
+        if (!XL[i].diag) continue;              // instance skipped
+        const Instance& I = h->inst[i];
+        if (!I.factored) {
+            return set_err(h, BT_ERR_STATE, "instance " + std::to_string(i) + ": selected_solve before factor");
+        }
+        if (!check_blocks(I.D, &B[i], true, msg, "B") || !check_blocks(I.D, &XL[i], true, msg, "XL"))
+            return set_err(h, BT_ERR_INVALID, "instance " + std::to_string(i) + ": " + msg);
+        sel.push_back(i);
+    }
+    for (int i = 0; i < count; ++i) { Au[i] = h->inst[i].A_used; XRu[i] = h->inst[i].XR_used; }
+    if (sel.empty()) return BT_OK;
+    return run_instances(h, MODE_SQ, sel, Au.data(), B, XRu.data(), XL, err_estimates, used_fp64_fallback);
+}
+
+int32_t bt_si_sq_batch_count(bt_si_sq_handle h) { return h ? (int32_t)h->inst.size() : 0; }
 
 bt_status bt_si_sq_sync(bt_si_sq_handle h) {
     if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
@@ -1251,9 +1605,15 @@ bt_status bt_si_sq_sync(bt_si_sq_handle h) {
     if (s.code != 0) {
         DevStatus z{0, 0};
         hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
-        char buf[160];
-        snprintf(buf, sizeof buf, "singular or non-finite pivot while inverting diagonal block %d%s", s.tag,
-                 s.tag == h->D.n ? " (arrow tip)" : "");
+        const int inst = s.tag >> 16, blk = s.tag & 0xffff;
+        const bool tip = inst < (int)h->inst.size() && blk == h->inst[inst].D.n;
+        char buf[200];
+        if (h->inst.size() > 1)
+            snprintf(buf, sizeof buf, "singular or non-finite pivot while inverting diagonal block %d%s of instance %d",
+                     blk, tip ? " (arrow tip)" : "", inst);
+        else
+            snprintf(buf, sizeof buf, "singular or non-finite pivot while inverting diagonal block %d%s",
+                     blk, tip ? " (arrow tip)" : "");
         return set_err(h, BT_ERR_SINGULAR, buf);
     }
     h->err.clear();
@@ -1264,15 +1624,12 @@ bt_status bt_si_sq_destroy(bt_si_sq_handle h) {
     if (!h) return BT_OK;
     hipStreamSynchronize(h->stream);
     hipStreamSynchronize(h->astream);
-    for (auto& c : h->cache) {
-        if (c.dev) hipFree(c.dev);
-        for (auto ev : c.events) hipEventDestroy(ev);
-    }
+    for (auto& c : h->cache) free_cached(h, c);
+    if (h->host_stage) hipHostFree(h->host_stage);
+    if (h->upload_done) hipEventDestroy(h->upload_done);
     if (h->ev_start) hipEventDestroy(h->ev_start);
     if (h->ev_end) hipEventDestroy(h->ev_end);
     if (h->astream) hipStreamDestroy(h->astream);
-    if (h->host_stage) hipHostFree(h->host_stage);
-    if (h->upload_done) hipEventDestroy(h->upload_done);
     for (auto ev : h->ev_pool) hipEventDestroy(ev);
     hipFree(h->ws);
     hipFree(h->inv_pool);
@@ -1290,6 +1647,7 @@ int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h) { return h ? h->last_launc
 bt_status bt_si_sq_profile(bt_si_sq_handle h, int32_t enable) {
     if (!h) return set_err(nullptr, BT_ERR_INVALID, "null handle");
     hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->astream);
     if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
     h->pending.clear();
     h->ev_used = 0;
@@ -1302,6 +1660,7 @@ bt_status bt_si_sq_profile_stats(bt_si_sq_handle h, bt_kernel_stat* out, int32_t
                                  int32_t* count) {
     if (!h || !count || (max_entries > 0 && !out)) return set_err(h, BT_ERR_INVALID, "bad arguments");
     hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->astream);
     if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
     collect_profile(h);
     int32_t c = 0;
@@ -1406,8 +1765,8 @@ bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t c
                                : launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s);
                 break;
             case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
-            case 2: e = launch_inv_panel(dj + L.off, L.count, L.maxd, L.panel, st, s); break;
             case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
+            case 6: e = launch_inv_step(dj + L.off, L.count, L.maxd, L.panel, L.tiles, st, s); break;
             default: break;
         }
     }

@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BT_FP64, BT_MIXED, BTError, check, make_desc
+from ._lib import BT_FP64, BT_MIXED, BT_PLAIN, BTError, check, make_desc
 
 FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
 
@@ -95,10 +95,10 @@ class Solver:
     """bt_si_sq_create / _factor / _selected_solve / _solve / _sync / _destroy."""
 
     def __init__(self, n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, tol=1e-4,
-                 stream=None):
+                 stream=None, flags=0):
         torch = _torch()
         self.n, self.b, self.a = n, b, a
-        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol)
+        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol, flags)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         check(_lib.lib().bt_si_sq_create(C.byref(self._desc), C.c_void_p(self.stream.cuda_stream),
@@ -161,8 +161,83 @@ class Solver:
             pass
 
 
-__all__ = ["DeviceBlocks", "Solver", "workspace_bytes", "partition_bounds", "flops",
-           "BT_FP64", "BT_MIXED", "BTError"]
+class BatchSolver:
+    """bt_si_sq_batch_create / _batch_solve: many uneven instances in one schedule.
+
+    specs: list of dicts with n, b, a and optionally partitions, bounds,
+    precision, tol.
+    """
+
+    def __init__(self, specs, stream=None):
+        torch = _torch()
+        self.count = len(specs)
+        self._descs = [make_desc(sp["n"], sp["b"], sp.get("a", 0), sp.get("partitions", 1),
+                                 sp.get("bounds"), sp.get("precision", BT_FP64), sp.get("tol", 1e-4),
+                                 sp.get("flags", 0))
+                       for sp in specs]
+        arr = (_lib.bt_desc * self.count)(*self._descs)
+        self._arr = arr
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        check(_lib.lib().bt_si_sq_batch_create(self.count, arr, C.c_void_p(self.stream.cuda_stream),
+                                               C.byref(h)))
+        self._h = h
+
+    def solve(self, A, B, XR, XL):
+        """Lists of DeviceBlocks (XR may be None).  Returns (err_estimates, used_fp64_fallback)."""
+        n = self.count
+
+        def arr(ms):
+            if ms is None:
+                return None
+            return (_lib.bt_blocks * n)(*[m.c_blocks() for m in ms])
+
+        self._keep = (A, B, XR, XL)
+        err = (C.c_double * n)()
+        fb = (C.c_int * n)()
+        check(_lib.lib().bt_si_sq_batch_solve(self._h, arr(A), arr(B), arr(XR), arr(XL), err, fb),
+              self._h)
+        return list(err), [bool(x) for x in fb]
+
+    def selected_solve(self, B, XL):
+        """New right-hand sides on the resident factors; entries of XL may be None (skipped)."""
+        n = self.count
+        empty = _lib.bt_blocks()
+        barr = (_lib.bt_blocks * n)(*[(b.c_blocks() if b is not None else empty) for b in B])
+        larr = (_lib.bt_blocks * n)(*[(x.c_blocks() if x is not None else empty) for x in XL])
+        self._keep2 = (B, XL)
+        err = (C.c_double * n)()
+        fb = (C.c_int * n)()
+        check(_lib.lib().bt_si_sq_batch_selected_solve(self._h, barr, larr, err, fb), self._h)
+        return list(err), [bool(x) for x in fb]
+
+    def sync(self):
+        check(_lib.lib().bt_si_sq_sync(self._h), self._h)
+
+    def last_launch_count(self) -> int:
+        return int(_lib.lib().bt_si_sq_last_launch_count(self._h))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _lib.lib().bt_si_sq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(specs) -> int:
+    descs = [make_desc(sp["n"], sp["b"], sp.get("a", 0), sp.get("partitions", 1), sp.get("bounds"),
+                       sp.get("precision", BT_FP64), sp.get("tol", 1e-4)) for sp in specs]
+    arr = (_lib.bt_desc * len(descs))(*descs)
+    return int(_lib.lib().bt_si_sq_batch_workspace_bytes(len(descs), arr))
+
+
+__all__ = ["DeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
+           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BTError"]
 
 
 def diag_gemm(alpha, A, opA, B, opB, beta=0.0, Cin=None, D=None, mixed=False, stream=None):

@@ -1,0 +1,75 @@
+"""Batched uneven instances in one schedule: each result equals the oracle
+(FP64 bar 1e-11, mixed bar 1e-4 or FP64 re-run) and equals the same
+instance solved alone (bitwise for FP64: the products of an instance do not
+depend on what else shares the launch)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_04904_amd.synth import gen_problem
+from tests._util import rel_err
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2601_04904_amd import solver
+    return solver
+
+
+SPECS = [
+    dict(n=9, b=64, a=0, partitions=1, E=0.2, seed=1),
+    dict(n=14, b=32, a=16, partitions=2, E=-0.5, seed=2),
+    dict(n=5, b=96, a=40, partitions=1, E=0.9, seed=3),
+    dict(n=12, b=48, a=0, partitions=3, E=0.0, seed=4),
+    dict(n=1, b=20, a=7, partitions=1, E=0.4, seed=5),
+]
+
+
+def _solve_batch(S, specs, problems):
+    dA = [S.DeviceBlocks.from_host(A) for A, _ in problems]
+    dB = [S.DeviceBlocks.from_host(B) for _, B in problems]
+    XR = [S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]) for sp in specs]
+    XL = [S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]) for sp in specs]
+    bs = S.BatchSolver(specs)
+    err, fb = bs.solve(dA, dB, XR, XL)
+    bs.sync()
+    out = [(x.to_host(), y.to_host()) for x, y in zip(XR, XL)]
+    bs.destroy()
+    return out, err, fb
+
+
+def test_batch_fp64_matches_oracle_and_alone(S):
+    problems = [gen_problem(sp["n"], sp["b"], sp["a"], E=sp["E"], eta=1e-3, seed=sp["seed"]) for sp in SPECS]
+    out, err, fb = _solve_batch(S, SPECS, problems)
+    for sp, (A, B), (XR, XL) in zip(SPECS, problems, out):
+        R0, L0 = oracle.solve_dense(A, B)
+        eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+        print(sp, f"R={eR:.2e} L={eL:.2e}", flush=True)
+        assert eR < 1e-11 and eL < 1e-11
+    # alone vs in the batch: identical bits
+    for i in (0, 3):
+        alone, _, _ = _solve_batch(S, [SPECS[i]], [problems[i]])
+        for f in FIELDS:
+            assert np.array_equal(getattr(alone[0][0], f), getattr(out[i][0], f)), f
+            assert np.array_equal(getattr(alone[0][1], f), getattr(out[i][1], f)), f
+
+
+def test_batch_mixed_and_fp64_instances(S):
+    specs = [dict(SPECS[0], precision=S.BT_MIXED), dict(SPECS[1]), dict(SPECS[2], precision=S.BT_MIXED, tol=1e-15)]
+    problems = [gen_problem(sp["n"], sp["b"], sp["a"], E=sp["E"], eta=1e-2, seed=sp["seed"]) for sp in specs]
+    out, err, fb = _solve_batch(S, specs, problems)
+    assert fb[2] is True            # tolerance 1e-15 forces the FP64 re-run
+    assert fb[1] is False and err[1] == 0.0
+    for k, (sp, (A, B), (XR, XL)) in enumerate(zip(specs, problems, out)):
+        R0, L0 = oracle.solve_dense(A, B)
+        e = max(rel_err(XR, R0), rel_err(XL, L0))
+        print(k, sp.get("precision", 0), e, err[k], fb[k], flush=True)
+        if sp.get("precision", 0) == S.BT_MIXED and not fb[k]:
+            assert e <= 1e-4
+        else:
+            assert e < 1e-11

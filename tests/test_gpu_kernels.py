@@ -127,3 +127,21 @@ def test_inverse_singular_is_flagged(torch):
     _, bad = diag_inverse(torch.from_numpy(M).cuda())
     torch.cuda.synchronize()
     assert bad == 1
+
+
+def test_inverse_pivot_choice_matters(torch):
+    """Each column has one large entry (1e3) in a random row and small ones (1e-3)
+    elsewhere: any pivot other than the largest entry costs about six digits,
+    so this checks the pivot search picks the maximum."""
+    from paper_2601_04904_amd.solver import diag_inverse
+    rng = np.random.default_rng(11)
+    for d in (64, 300, 512):
+        M = 1e-3 * crand(rng, d, d)
+        perm = rng.permutation(d)
+        M[perm, np.arange(d)] = 1e3 * (1.0 + rng.uniform(size=d)) * np.exp(2j * np.pi * rng.uniform(size=d))
+        dst, bad = diag_inverse(torch.from_numpy(M[None]).cuda())
+        torch.cuda.synchronize()
+        assert bad == -1
+        ref = np.linalg.inv(M)
+        err = np.linalg.norm(dst.cpu().numpy()[0] - ref) / np.linalg.norm(ref)
+        assert err < 1e-14 * np.sqrt(d) * 10, (d, err)
