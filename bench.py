@@ -289,6 +289,12 @@ def main():
         achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
         roof = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=None)
+    elif dom_name.startswith("inv_panel"):
+        # Gauss-Jordan steps run on the FP64 vector units (pivot search and
+        # row updates); bound by FP64 VALU issue and by the per-column latency
+        achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None)
     else:
         achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",

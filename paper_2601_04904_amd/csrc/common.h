@@ -50,8 +50,7 @@ struct InvJob {
 };
 
 constexpr int kInvNB = 16;          // panel width (panel rows live in registers)
-constexpr int kInvThreads = 512;    // threads of the panel kernel
-constexpr int kInvMaxDim = 1024;    // 2 rows per thread at most
+constexpr int kInvMaxDim = 1024;    // 512 threads x 2 rows at most
 
 // D = sum_j c_j X_j (elementwise, rows x cols, leading dimensions = cols).
 constexpr int kMaxAdd = 17;

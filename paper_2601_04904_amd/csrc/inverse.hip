@@ -10,13 +10,15 @@
 //     A^-1[j][c] = W[p_j][pinv(c)].
 //
 // Blocking: a panel of kInvNB columns is eliminated by one workgroup that
-// holds the panel rows in registers (one barrier per column: every wave
-// publishes its best candidate row, every thread then picks the winner).  The
+// holds the panel rows in registers (one barrier per column: the best
+// candidate of every wave publishes its row and the reciprocal of its pivot
+// entry, every thread then picks the winner and updates its rows).  The
 // effect of the panel on the other columns is M_J = I + Mm Y, where
 //     Mm[:, s] = (panel column s) - e_{p_s}   (d x NB)
 //     Y[s, :]  = W[p_s, :] outside the panel, 0 inside (NB x d),
 // applied by the grouped product kernel as W += Mm Y.
 #include "common.h"
+#include <cfloat>
 #include <climits>
 
 namespace btsq {
@@ -25,14 +27,30 @@ __device__ inline double2 cmul_i(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// 1 / v by Smith's algorithm (no overflow for large |v|).
+// acc += a b and acc -= a b, four fused multiply-adds each
+__device__ inline void cfma(double2& acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
+__device__ inline void cfms(double2& acc, double2 a, double2 b) {
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+
+// 1 / v = conj(v) / |v|^2, with v first scaled by a power of two so that
+// |v|^2 neither overflows nor underflows (one division).  A zero, infinite
+// or NaN v gives a non-finite or zero result, which the caller flags.
 __device__ inline double2 crecip(double2 v) {
-    if (fabs(v.x) >= fabs(v.y)) {
-        const double r = v.y / v.x, den = v.x + v.y * r;
-        return make_double2(1.0 / den, -r / den);
-    }
-    const double r = v.x / v.y, den = v.x * r + v.y;
-    return make_double2(r / den, -1.0 / den);
+    int e;
+    (void)frexp(fmax(fabs(v.x), fabs(v.y)), &e);
+    const double a = ldexp(v.x, -e), b = ldexp(v.y, -e);
+    const double inv = 1.0 / (a * a + b * b);
+    return make_double2(ldexp(a * inv, -e), ldexp(-b * inv, -e));
 }
 
 // Maximum over the 64 lanes of a wave, by DPP moves (both halves of the
@@ -59,6 +77,22 @@ __device__ inline double wave_max(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Pivot key: |re| + |im| of the candidate (non-finite values clamped to the
+// largest finite double) with the 11 low mantissa bits replaced by
+// 2047 - row.  Non-negative doubles order like their bit patterns, so the
+// largest key is the largest magnitude (to 41 mantissa bits) and, among
+// magnitudes equal to that precision, the lowest row.  No candidate: -1.
+__device__ inline double pivot_key(double2 v, int row) {
+    double m = fabs(v.x) + fabs(v.y);
+    if (!(m <= DBL_MAX)) m = DBL_MAX;
+    const long long b = (__double_as_longlong(m) & ~2047ll) | (long long)(2047 - row);
+    return __longlong_as_double(b);
+}
+
+__device__ inline int key_row(double key) {
+    return 2047 - (int)(__double_as_longlong(key) & 2047ll);
+}
+
 __global__ void inv_init(const InvJob* __restrict__ jobs) {
     const InvJob J = jobs[blockIdx.y];
     const size_t total = (size_t)J.d * J.d;
@@ -77,10 +111,9 @@ __global__ void inv_init(const InvJob* __restrict__ jobs) {
 // Mm is double-buffered by panel parity (Mm + (p % 2) * d * NB).
 constexpr int kUpdCols = 8;
 
-template <int R>
+template <int T, int R>
 __device__ void step_update(const InvJob& J, int p, int u, int tid) {
     constexpr int NB = kInvNB;
-    constexpr int T = kInvThreads;
     constexpr int UC = kUpdCols;
     __shared__ double2 G[NB][UC];
     const int d = J.d;
@@ -117,9 +150,7 @@ __device__ void step_update(const InvJob& J, int p, int u, int tid) {
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < UC; ++j) {
-                    const double2 g = G[s + i][j];
-                    acc[j].x += m[i].x * g.x - m[i].y * g.y;
-                    acc[j].y += m[i].x * g.y + m[i].y * g.x;
+                    cfma(acc[j], m[i], G[s + i][j]);
                 }
         }
         double2* wout = J.W + (size_t)r * d + c0;
@@ -129,15 +160,15 @@ __device__ void step_update(const InvJob& J, int p, int u, int tid) {
     }
 }
 
-template <int R>
+template <int T, int R>
 __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     constexpr int NB = kInvNB;
-    constexpr int T = kInvThreads;
     constexpr int NW = T / 64;
-    __shared__ double cand_v[2][NW];
-    __shared__ int cand_r[2][NW];
+    __shared__ double cand_key[2][NW];
+    __shared__ double2 cand_ip[2][NW];
     __shared__ double2 cand_row[2][NW][NB];
     __shared__ int piv[NB];
+    __shared__ int prev[NB];
     __shared__ double2 G[NB][NB];
 
     const int d = J.d;
@@ -146,6 +177,9 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     const int nc = min(NB, d - j0);
     const int lane = tid & 63, wave = tid >> 6;
 
+    // All global reads are issued here, before any wait: this workgroup's rows
+    // of block p, their used flags, their rows of the panel p-1 transform and
+    // the pivot rows of panel p-1.
     double2 P[R][NB];
     int used[R];
 #pragma unroll
@@ -156,36 +190,58 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
 #pragma unroll
         for (int c = 0; c < NB; ++c) P[q][c] = row[min(c, nc - 1)];
     }
-    // look-ahead: apply the transform of panel p-1 to this block
     if (p > 0) {
         const int q0 = (p - 1) * NB;
         const int pnc = min(NB, d - q0);
-        if (tid < NB * NB) {
-            const int s = tid / NB, c = tid % NB;
-            const int sr = min(s, pnc - 1), cc = min(c, nc - 1);
-            const double2 v = J.W[(size_t)J.perm[q0 + sr] * d + j0 + cc];
-            G[s][c] = (s < pnc && c < nc) ? v : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
+        constexpr int MG = R == 1 ? NB : 4;          // transform entries held at once
         const double2* Mm = J.Mm + (size_t)((p - 1) & 1) * d * NB;
+        double2 m[R][MG];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int r = min(tid + q * T, d - 1);
-            const double2* mrow = Mm + (size_t)r * NB;
-#pragma unroll 2
-            for (int s = 0; s < NB; s += 4) {
-                double2 m[4];
+            const double2* mrow = Mm + (size_t)min(tid + q * T, d - 1) * NB;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) m[i] = mrow[s + i];
+            for (int i = 0; i < MG; ++i) m[q][i] = mrow[i];
+        }
+        if (tid < NB) prev[tid] = tid < pnc ? J.perm[q0 + tid] : -1;
+        if (tid < NB && tid >= pnc) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+            for (int c = 0; c < NB; ++c) G[tid][c] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        // The pivot rows of panel p-1 restricted to block p (not yet
+        // transformed) come from the threads that hold them.  Columns past nc
+        // of G only reach columns of P that are cleared below.
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) {
-                        const double2 g = G[s + i][c];
-                        P[q][c].x += m[i].x * g.x - m[i].y * g.y;
-                        P[q][c].y += m[i].x * g.y + m[i].y * g.x;
-                    }
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + q * T;
+            int sm = -1;
+#pragma unroll
+            for (int s = 0; s < NB; ++s) sm = prev[s] == r ? s : sm;
+            if (sm >= 0 && r < d) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) G[sm][c] = P[q][c];
             }
+        }
+        __syncthreads();
+        // look-ahead: block p += Mm_{p-1} G
+#pragma unroll
+        for (int s0 = 0; s0 < NB; s0 += MG) {
+            if (s0 > 0) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const double2* mrow = Mm + (size_t)min(tid + q * T, d - 1) * NB;
+#pragma unroll
+                    for (int i = 0; i < MG; ++i) m[q][i] = mrow[s0 + i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < MG; ++i)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    const double2 g = G[s0 + i][c];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) cfma(P[q][c], m[q][i], g);
+                }
         }
     }
 #pragma unroll
@@ -197,81 +253,73 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
             if (!rin || c >= nc) P[q][c] = make_double2(0.0, 0.0);
     }
 
+    // Column loop, fully unrolled so that every register index is static.
+    bool bad = false;
+#pragma unroll
     for (int s = 0; s < NB; ++s) {
         if (s < nc) {
             const int sb = s & 1;
-            // candidate of this lane: largest |re| + |im| among its unused rows
-            // (rows ascend with q, so ties keep the lower row)
-            double bv = -1.0;
-            int br = INT_MAX;
+            // candidate key of this lane over its unused rows
+            double bk = -1.0;
+            int bq = 0;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const int r = tid + q * T;
-                if (r < d && !used[q]) {
-                    double v = fabs(P[q][0].x) + fabs(P[q][0].y);
-                    if (!(v >= 0.0)) v = INFINITY;   // NaN: make it win, and be flagged
-                    if (v > bv) { bv = v; br = r; }
-                }
+                const double k = used[q] ? -1.0 : pivot_key(P[q][s], tid + q * T);
+                if (k > bk) { bk = k; bq = q; }
             }
-            // wave maximum, then the lowest lane holding it
-            const double wmax = wave_max(bv);
-            const unsigned long long hit = __ballot(bv == wmax && br != INT_MAX);
-            if (hit == 0ull) {
-                if (lane == 0) { cand_v[sb][wave] = -1.0; cand_r[sb][wave] = INT_MAX; }
-            } else if (lane == (int)__builtin_ctzll(hit)) {
-                const int qo = br / T;
-                cand_v[sb][wave] = bv;
-                cand_r[sb][wave] = br;
+            // the wave's best key (unique: keys carry the row); its lane
+            // publishes the row and the reciprocal of its pivot entry
+            const double wk = wave_max(bk);
+            if (bk == wk) {
+                if (wk < 0.0) {
+                    if (lane == 0) cand_key[sb][wave] = -1.0;
+                } else {
+                    cand_key[sb][wave] = wk;
 #pragma unroll
-                for (int q = 0; q < R; ++q)
-                    if (q == qo) {
+                    for (int q = 0; q < R; ++q)
+                        if (q == bq) {
+                            cand_ip[sb][wave] = crecip(P[q][s]);
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) cand_row[sb][wave][c] = P[q][c];
-                    }
+                            for (int c = 0; c < NB; ++c) cand_row[sb][wave][c] = P[q][c];
+                        }
+                }
             }
             __syncthreads();
-            double gv = -1.0;
-            int gr = INT_MAX, gw = 0;
+            double gk = cand_key[sb][0];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const double v = cand_v[sb][w];
-                const int r = cand_r[sb][w];
-                if (v > gv || (v == gv && r < gr)) { gv = v; gr = r; gw = w; }
-            }
-            if (!(gv > 0.0) || gv == INFINITY) {
-                if (tid == 0 && atomicCAS(&status->code, 0, 3) == 0) status->tag = J.tag;
-            }
-            const double2 ip = crecip(cand_row[sb][gw][0]);
-            double2 f[R];
+            for (int w = 1; w < NW; ++w) gk = fmax(gk, cand_key[sb][w]);
+            const int gr = gk < 0.0 ? -1 : key_row(gk);
+            const int gw = gk < 0.0 ? 0 : (gr % T) >> 6;
+            const double2 ip = cand_ip[sb][gw];
+            bad = bad || gk < 0.0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX) || (ip.x == 0.0 && ip.y == 0.0);
+            double2 g[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) f[q] = P[q][0];
+            for (int q = 0; q < R; ++q) g[q] = cmul_i(P[q][s], ip);
+            // every row: row -= (f / pivot) * pivot row; the pivot column slot
+            // takes -f / pivot
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                const double2 spc = (c == 0) ? ip : cmul_i(cand_row[sb][gw][c], ip);
+                if (c == s) continue;
+                const double2 v = cand_row[sb][gw][c];
 #pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int r = tid + q * T;
-                    const double2 t = cmul_i(f[q], spc);
-                    const double ux = (c == 0) ? -t.x : P[q][c].x - t.x;
-                    const double uy = (c == 0) ? -t.y : P[q][c].y - t.y;
-                    const bool piv_row = r == gr;
-                    P[q][c].x = piv_row ? spc.x : ux;
-                    P[q][c].y = piv_row ? spc.y : uy;
-                }
+                for (int q = 0; q < R; ++q) cfms(P[q][c], g[q], v);
             }
 #pragma unroll
-            for (int q = 0; q < R; ++q)
-                if (tid + q * T == gr) used[q] = 1;
-            if (tid == 0) piv[s] = gr;
-        }
+            for (int q = 0; q < R; ++q) {
+                P[q][s] = make_double2(-g[q].x, -g[q].y);
+                if (tid + q * T == gr) {
+                    // the pivot row itself: scaled by 1 / pivot, its pivot
+                    // column slot takes 1 / pivot
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const double2 first = P[q][0];
-#pragma unroll
-            for (int c = 0; c < NB - 1; ++c) P[q][c] = P[q][c + 1];
-            P[q][NB - 1] = first;
+                    for (int c = 0; c < NB; ++c)
+                        P[q][c] = c == s ? ip : cmul_i(cand_row[sb][gw][c], ip);
+                    used[q] = 1;
+                }
+            }
+            if (tid == 0) piv[s] = gr < 0 ? 0 : gr;
         }
     }
+    if (bad && tid == 0 && atomicCAS(&status->code, 0, 3) == 0) status->tag = J.tag;
     __syncthreads();
     double2* Mm = J.Mm + (size_t)(p & 1) * d * NB;
 #pragma unroll
@@ -298,14 +346,14 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
 }
 
 // grid.x = njobs * wg_per_job; workgroup 0 of a job is the panel workgroup.
-template <int R>
-__global__ __launch_bounds__(kInvThreads)
+template <int T, int R>
+__global__ __launch_bounds__(T)
 void inv_step(const InvJob* __restrict__ jobs, int p, int wg_per_job, DevStatus* status) {
     const int job = blockIdx.x / wg_per_job;
     const int w = blockIdx.x - job * wg_per_job;
     const InvJob J = jobs[job];
-    if (w == 0) step_panel<R>(J, p, threadIdx.x, status);
-    else if (p > 0) step_update<R>(J, p, w - 1, threadIdx.x);
+    if (w == 0) step_panel<T, R>(J, p, threadIdx.x, status);
+    else if (p > 0) step_update<T, R>(J, p, w - 1, threadIdx.x);
 }
 
 __global__ void inv_finish(const InvJob* __restrict__ jobs) {
@@ -333,14 +381,17 @@ hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel, int maxd,
+int inv_variant(int d) { return d <= 256 ? 0 : d <= 512 ? 1 : 2; }
+
+hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int panel, int maxd,
                            DevStatus* status, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     const int wg = 1 + (maxd + kUpdCols - 1) / kUpdCols;
-    if (rows_per_thread == 1)
-        hipLaunchKernelGGL(inv_step<1>, dim3(njobs * wg), dim3(kInvThreads), 0, s, d_jobs, panel, wg, status);
-    else
-        hipLaunchKernelGGL(inv_step<2>, dim3(njobs * wg), dim3(kInvThreads), 0, s, d_jobs, panel, wg, status);
+    switch (variant) {
+        case 0: hipLaunchKernelGGL((inv_step<256, 1>), dim3(njobs * wg), dim3(256), 0, s, d_jobs, panel, wg, status); break;
+        case 1: hipLaunchKernelGGL((inv_step<256, 2>), dim3(njobs * wg), dim3(256), 0, s, d_jobs, panel, wg, status); break;
+        default: hipLaunchKernelGGL((inv_step<512, 2>), dim3(njobs * wg), dim3(512), 0, s, d_jobs, panel, wg, status); break;
+    }
     return hipGetLastError();
 }
 

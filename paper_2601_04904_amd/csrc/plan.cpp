@@ -42,7 +42,8 @@ int gemm_tiles(int m, int n);
 int gemm_tiles_n(int n);
 hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
 hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
-hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int rows_per_thread, int panel, int maxd,
+int inv_variant(int d);   // panel kernel shape for dimension d: 0 (256 x 1 rows), 1 (256 x 2), 2 (512 x 2)
+hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int panel, int maxd,
                            DevStatus* status, hipStream_t s);
 hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s);
 hipError_t launch_gemm32(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s);
@@ -657,12 +658,12 @@ int levelize(std::vector<OpRec>& ops, bool plain = false) {
 }
 
 struct Launch {
-    int type;         // 0 gemm, 1 inv_init, 2 inv_panel, 3 inv_finish, 4 add
+    int type;         // 0 gemm, 1 inv_init, 3 inv_finish, 4 add, 5 norms, 6 inverse panel step
     size_t off;       // element offset into the typed array
     int count;
     int tiles;        // gemm: total tiles
     int mixed;        // gemm precision
-    int maxd;         // inverse: max dim; panel: rows per thread
+    int maxd;         // inverse: max dim; panel step: kernel shape (inv_variant)
     int panel;
     size_t maxelems;  // add
     double flops = 0; // algorithmic work of the launch
@@ -764,14 +765,14 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
     };
     for (int L = 0; L < nlevels; ++L) {
         for (int cls = 1; cls >= 0; --cls) {
-            // inverses (grouped by rows per thread of the panel kernel)
+            // inverses (grouped by the shape of the panel kernel)
             std::vector<int> invs;
             int wait = -1;
             for (int i : bylevel[L])
                 if (ops[i].kind == K_INV && ops[i].cls == cls) { invs.push_back(i); wait = std::max(wait, ops[i].wait_other); }
             if (!invs.empty()) {
                 std::stable_sort(invs.begin(), invs.end(), [&](int x, int y) {
-                    return (ops[x].D.r > 512) < (ops[y].D.r > 512);
+                    return inv_variant(ops[x].D.r) < inv_variant(ops[y].D.r);
                 });
                 size_t poff = 0;
                 const size_t first = pg.inv.size();
@@ -795,22 +796,21 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                 }
                 pg.inv_scratch_bytes = std::max(pg.inv_scratch_bytes, poff + 256);
                 const int nj = (int)invs.size();
-                int n1 = 0, maxd1 = 0, maxd2 = 0;
+                int vcount[3] = {0, 0, 0}, vmaxd[3] = {0, 0, 0};
                 for (int i : invs) {
-                    if (ops[i].D.r <= 512) { ++n1; maxd1 = std::max(maxd1, ops[i].D.r); }
-                    else maxd2 = std::max(maxd2, ops[i].D.r);
+                    const int v = inv_variant(ops[i].D.r);
+                    ++vcount[v];
+                    vmaxd[v] = std::max(vmaxd[v], ops[i].D.r);
                 }
                 pg.launches.push_back(mk(1, first, nj, 0, 0, maxd, 0, 0, cls, L, wait));
-                // one launch per panel (plus one that applies the last panel)
+                // one launch per panel and kernel shape (plus one that applies the last panel)
                 const int npanels = (maxd + kInvNB - 1) / kInvNB;
                 for (int p = 0; p <= npanels; ++p) {
-                    if (n1 > 0 && p <= (maxd1 + kInvNB - 1) / kInvNB) {
-                        Launch sl = mk(6, first, n1, maxd1, 0, 1, p, 0, cls, L, -1);
-                        pg.launches.push_back(sl);
-                    }
-                    if (nj - n1 > 0 && p <= (maxd2 + kInvNB - 1) / kInvNB) {
-                        Launch sl = mk(6, first + n1, nj - n1, maxd2, 0, 2, p, 0, cls, L, -1);
-                        pg.launches.push_back(sl);
+                    size_t off = first;
+                    for (int v = 0; v < 3; ++v) {
+                        if (vcount[v] > 0 && p <= (vmaxd[v] + kInvNB - 1) / kInvNB)
+                            pg.launches.push_back(mk(6, off, vcount[v], vmaxd[v], 0, v, p, 0, cls, L, -1));
+                        off += vcount[v];
                     }
                 }
                 pg.launches.push_back(mk(3, first, nj, 0, 0, maxd, 0, 0, cls, L, -1));
@@ -903,16 +903,6 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
     for (Launch& L : pg.launches) {
         if (L.type == 0) {
             gemm_work(pg.gemm.data() + L.off, L.count, L.flops, L.bytes);
-        } else if (L.type == 2) {
-            // panel: each eliminated column updates the panel rows (8 flops per complex
-            // multiply-add, nb columns): d * nb * nb complex MACs per job
-            for (int q = 0; q < L.count; ++q) {
-                const InvJob& j = pg.inv[L.off + q];
-                if (L.panel * kInvNB >= j.d) continue;
-                const double nc = std::min(kInvNB, j.d - L.panel * kInvNB);
-                L.flops += 8.0 * j.d * nc * nc;
-                L.bytes += 16.0 * (2.0 * j.d * nc + 2.0 * j.d * kInvNB + 2.0 * kInvNB * j.d);
-            }
         } else if (L.type == 6) {
             for (int q = 0; q < L.count; ++q) {
                 const InvJob& j = pg.inv[L.off + q];
@@ -1109,7 +1099,6 @@ int kernel_kind(const Launch& L) {
     switch (L.type) {
         case 0: return L.mixed ? BT_KERNEL_PRODUCT_MIXED : BT_KERNEL_PRODUCT_FP64;
         case 1: return BT_KERNEL_INV_INIT;
-        case 2: return BT_KERNEL_INV_PANEL;
         case 3: return BT_KERNEL_INV_FINISH;
         case 5: return BT_KERNEL_NORM;
         case 6: return BT_KERNEL_INV_PANEL;
