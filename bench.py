@@ -6,7 +6,11 @@ SQ sweeps) of the workload, with A and B already resident in HBM.  Prints one
 JSON line.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload bt_n64_b512]
-                    [--partitions P] [--compare-partitions Q] [--no-cpu-baseline]
+                    [--partitions P] [--compare-partitions Q ...] [--no-cpu-baseline]
+
+Without --partitions every form the workload names is timed (sequential RGF
+and the partitioned variant); the value is the fastest of them and the others
+are reported beside it.
 """
 from __future__ import annotations
 
@@ -219,11 +223,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bt_n64_b512")
+    ap.add_argument("--workload", default="bt_n64_b512",
+                    help="bt_n16_b32 | bt_n64_b512 | bta_n128_b384_a512 | batch | serve | copy")
     ap.add_argument("--partitions", type=int, default=None,
-                    help="partitions of the timed solve (default: the workload's first entry)")
-    ap.add_argument("--compare-partitions", type=int, default=None,
-                    help="also time this partition count and report it beside the headline")
+                    help="time only this partition count (default: every form the workload names)")
+    ap.add_argument("--compare-partitions", type=int, nargs="*", default=None,
+                    help="also time these partition counts and report them beside the value")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -253,28 +258,54 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.workload == "copy":
+        # calibration for HBM traffic counters: a plain device copy of known size
+        nbytes = 1 << 30
+        x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 3
+        print(json.dumps({"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                          "copies": 3, "GB_per_s": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+        return
     if args.workload == "batch":
         return bench_batch(args, torch, S)
     if args.workload == "serve":
         return bench_serve(args, torch, S)
     cfg = CONFIGS[args.workload]
-    P = args.partitions if args.partitions is not None else cfg.partitions[0]
     n, b, a = cfg.n, cfg.b, cfg.a
-    log(f"[bench] workload {cfg.name}: n={n} b={b} a={a} P={P} eta={cfg.eta}")
+    # the forms the workload names (e.g. sequential and P=8); the value is the
+    # fastest of them, the others are reported beside it
+    forms = [args.partitions] if args.partitions is not None else list(cfg.partitions)
+    extra = [q for q in (args.compare_partitions or []) if q not in forms]
+    log(f"[bench] workload {cfg.name}: n={n} b={b} a={a} forms P={forms} extra P={extra} eta={cfg.eta}")
     t0 = time.perf_counter()
     A, B = gen_problem(n, b, a, cfg.E, cfg.eta, cfg.seed)
     log(f"[bench] generated inputs in {time.perf_counter() - t0:.1f} s")
     dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
     XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
 
-    sol = S.Solver(n, b, a, partitions=P)
-    elapsed, lat = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
-    launches = sol.last_launch_count()
+    timed = {}
+    for P in forms + extra:
+        sol = S.Solver(n, b, a, partitions=P)
+        el, lt = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
+        exP, usP = S.flops(n, b, a, P)
+        timed[P] = dict(elapsed=el, lat=lt, launches=sol.last_launch_count(), ex=exP, us=usP)
+        sol.destroy()
+        log(f"[bench] P={P}: {1e3 * el / args.steps:.2f} ms/solve, {timed[P]['launches']} launches/solve")
+    P = min(forms, key=lambda q: timed[q]["elapsed"])
+    elapsed, lat, launches = timed[P]["elapsed"], timed[P]["lat"], timed[P]["launches"]
+    ex, us = timed[P]["ex"], timed[P]["us"]
     ms = 1e3 * elapsed / args.steps
-    ex, us = S.flops(n, b, a, P)
-    log(f"[bench] P={P}: {ms:.2f} ms/solve, {launches} launches/solve")
 
-    # roofline of the dominant kernel, from HIP events around each launch
+    # roofline of the dominant kernel of the reported form, from HIP events
+    # recorded around each launch on the stream it runs on
+    sol = S.Solver(n, b, a, partitions=P)
+    sol.solve(dA, dB, XR, XL)
     sol.profile(True)
     for _ in range(args.profile_steps):
         sol.solve(dA, dB, XR, XL)
@@ -303,22 +334,19 @@ def main():
     roof["launches_per_solve"] = dom["launches"] / args.profile_steps
     roof["avg_launch_us"] = round(per_launch_ms * 1e3, 2)
     kernel_share = {k: round(v["total_ms"] / args.profile_steps, 3) for k, v in stats.items()}
-    log(f"[bench] per-solve kernel ms: {kernel_share}")
+    log(f"[bench] P={P} per-solve kernel ms: {kernel_share}")
+    sol.destroy()
 
-    compare = None
-    if args.compare_partitions is not None and args.compare_partitions != P:
-        Q = args.compare_partitions
-        solq = S.Solver(n, b, a, partitions=Q)
-        XR2, XL2 = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
-        el2, lat2 = time_solves(torch, solq, dA, dB, XR2, XL2, args.steps, args.warmup)
-        ex2, _ = S.flops(n, b, a, Q)
-        compare = dict(partitions=Q, solves_per_s=round(args.steps / el2, 4),
-                       ms_per_step=round(1e3 * el2 / args.steps, 3),
-                       pct_fp64_peak_executed=round(100 * ex2 / (el2 / args.steps) / 1e12 / FP64_PEAK_TFLOPS, 2),
-                       pct_fp64_peak_useful=round(100 * us / (el2 / args.steps) / 1e12 / FP64_PEAK_TFLOPS, 2))
-        log(f"[bench] P={Q}: {compare['ms_per_step']:.2f} ms/solve")
-        solq.destroy()
-        del XR2, XL2
+    def form_entry(q):
+        t = timed[q]
+        sec = t["elapsed"] / args.steps
+        return dict(partitions=q, solves_per_s=round(args.steps / t["elapsed"], 4),
+                    ms_per_step=round(1e3 * sec, 3), launches=t["launches"],
+                    pct_fp64_peak_executed=round(100 * t["ex"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
+                    pct_fp64_peak_useful=round(100 * t["us"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
+                    latency_ms={"p50": round(percentile(t["lat"], 50), 3),
+                                "p99": round(percentile(t["lat"], 99), 3)})
+    compare = {f"P{q}": form_entry(q) for q in forms + extra if q != P}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -357,7 +385,7 @@ def main():
         "cpu_baseline": cpu,
     }
     if compare:
-        out["compare"] = compare
+        out["other_forms"] = compare
     print(json.dumps(out), flush=True)
     sol.destroy()
 

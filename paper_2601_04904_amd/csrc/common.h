@@ -38,6 +38,18 @@ struct GemmOp {
 
 // One diagonal-block inverse dst = src^-1 (d x d) by blocked Gauss-Jordan
 // elimination with partial pivoting inside the block.
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This maps dispatch index b of a grid of g workgroups to a logical
+// index so that each XCD receives one contiguous range of logical indices,
+// i.e. neighbouring tiles (which share operand rows or columns) meet in the
+// same L2.  It is a bijection on [0, g).
+constexpr int kNumXcd = 8;
+__device__ inline int xcd_remap(int b, int g) {
+    const int xcd = b % kNumXcd, idx = b / kNumXcd;
+    const int per = g / kNumXcd, rem = g % kNumXcd;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 struct InvJob {
     const double2* src;
     double2* dst;

@@ -204,7 +204,7 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     __shared__ CT Bs[2][kBK][kBN + 1];
     __shared__ GemmTerm terms[kMaxTerms];
 
-    const int bid = blockIdx.x;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const GemmOp* op = ops + find_op(ops, nops, bid);
     const int m = op->m, n = op->n, nterms = op->nterms;
     const int local = bid - op->tile_begin;

@@ -20,6 +20,8 @@
 #include "common.h"
 #include <cfloat>
 #include <climits>
+#include <type_traits>
+#include <utility>
 
 namespace btsq {
 
@@ -253,74 +255,111 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
             if (!rin || c >= nc) P[q][c] = make_double2(0.0, 0.0);
     }
 
-    // Column loop, fully unrolled so that every register index is static.
-    bool bad = false;
+    // Candidate of this lane for column s (largest key over its unused rows),
+    // the wave maximum, and publication by the lane that holds it: the key,
+    // the reciprocal of its pivot entry and its whole row.
+    double bk, wk;
+    double2 bip;
+    int bq;
+    auto search = [&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        bk = -1.0;
+        bq = 0;
+        double2 pv = P[0][s];
 #pragma unroll
-    for (int s = 0; s < NB; ++s) {
-        if (s < nc) {
-            const int sb = s & 1;
-            // candidate key of this lane over its unused rows
-            double bk = -1.0;
-            int bq = 0;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const double k = used[q] ? -1.0 : pivot_key(P[q][s], tid + q * T);
-                if (k > bk) { bk = k; bq = q; }
-            }
-            // the wave's best key (unique: keys carry the row); its lane
-            // publishes the row and the reciprocal of its pivot entry
-            const double wk = wave_max(bk);
-            if (bk == wk) {
-                if (wk < 0.0) {
-                    if (lane == 0) cand_key[sb][wave] = -1.0;
-                } else {
-                    cand_key[sb][wave] = wk;
-#pragma unroll
-                    for (int q = 0; q < R; ++q)
-                        if (q == bq) {
-                            cand_ip[sb][wave] = crecip(P[q][s]);
-#pragma unroll
-                            for (int c = 0; c < NB; ++c) cand_row[sb][wave][c] = P[q][c];
-                        }
-                }
-            }
-            __syncthreads();
-            double gk = cand_key[sb][0];
-#pragma unroll
-            for (int w = 1; w < NW; ++w) gk = fmax(gk, cand_key[sb][w]);
-            const int gr = gk < 0.0 ? -1 : key_row(gk);
-            const int gw = gk < 0.0 ? 0 : (gr % T) >> 6;
-            const double2 ip = cand_ip[sb][gw];
-            bad = bad || gk < 0.0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX) || (ip.x == 0.0 && ip.y == 0.0);
-            double2 g[R];
-#pragma unroll
-            for (int q = 0; q < R; ++q) g[q] = cmul_i(P[q][s], ip);
-            // every row: row -= (f / pivot) * pivot row; the pivot column slot
-            // takes -f / pivot
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c == s) continue;
-                const double2 v = cand_row[sb][gw][c];
-#pragma unroll
-                for (int q = 0; q < R; ++q) cfms(P[q][c], g[q], v);
-            }
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                P[q][s] = make_double2(-g[q].x, -g[q].y);
-                if (tid + q * T == gr) {
-                    // the pivot row itself: scaled by 1 / pivot, its pivot
-                    // column slot takes 1 / pivot
-#pragma unroll
-                    for (int c = 0; c < NB; ++c)
-                        P[q][c] = c == s ? ip : cmul_i(cand_row[sb][gw][c], ip);
-                    used[q] = 1;
-                }
-            }
-            if (tid == 0) piv[s] = gr < 0 ? 0 : gr;
+        for (int q = 0; q < R; ++q) {
+            const double k = used[q] ? -1.0 : pivot_key(P[q][s], tid + q * T);
+            if (k > bk) { bk = k; bq = q; pv = P[q][s]; }
         }
-    }
+        bip = crecip(pv);
+        wk = wave_max(bk);
+    };
+    auto publish = [&](int sb) {
+        if (bk == wk) {
+            if (wk < 0.0) {
+                if (lane == 0) cand_key[sb][wave] = -1.0;
+            } else {
+                cand_key[sb][wave] = wk;
+                cand_ip[sb][wave] = bip;
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (q == bq) {
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) cand_row[sb][wave][c] = P[q][c];
+                    }
+            }
+        }
+    };
+    search(std::integral_constant<int, 0>{});
+    publish(0);
+
+    // Column loop, fully unrolled so that every register index is static.
+    // Column s + 1 is updated first, so that its pivot search and reciprocal
+    // overlap the update of the other columns.
+    //
+    // Pivot rows are not rescaled when they are chosen: every row is kept as
+    // sc * U, with U in registers and sc = 1 until the row becomes a pivot row,
+    // sc = 1 / pivot afterwards.  In U the update of any later column is then
+    // the same formula for every row (U -= (U[s] / pivot) v), the pivot row of
+    // column s only gets U[s] = 1 and skips the update of that column, and the
+    // scale is applied once, at write-back.
+    double2 sc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) sc[q] = make_double2(1.0, 0.0);
+    bool bad = false;
+    auto column = [&](auto scst) {
+        constexpr int s = decltype(scst)::value;
+        constexpr int sb = s & 1;
+        if (s >= nc) return;
+        __syncthreads();
+        double gk = cand_key[sb][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) gk = fmax(gk, cand_key[sb][w]);
+        const int gr = gk < 0.0 ? -1 : key_row(gk);
+        const int gw = gk < 0.0 ? 0 : (gr % T) >> 6;
+        const double2 ip = cand_ip[sb][gw];
+        bad = bad || gk < 0.0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX) || (ip.x == 0.0 && ip.y == 0.0);
+        double2 g[R];
+        bool pr[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            pr[q] = tid + q * T == gr;
+            const double2 t = cmul_i(P[q][s], ip);
+            g[q] = pr[q] ? make_double2(0.0, 0.0) : t;
+            if (pr[q]) { used[q] = 1; sc[q] = ip; }
+        }
+        // every other row: U -= (U[s] / pivot) * pivot row, column s + 1 first
+        const bool next = s + 1 < NB && s + 1 < nc;
+        if constexpr (s + 1 < NB) {
+            if (next) {
+                const double2 v = cand_row[sb][gw][s + 1];
+#pragma unroll
+                for (int q = 0; q < R; ++q) cfms(P[q][s + 1], g[q], v);
+                search(std::integral_constant<int, s + 1>{});
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c == s || c == s + 1) continue;
+            const double2 v = cand_row[sb][gw][c];
+#pragma unroll
+            for (int q = 0; q < R; ++q) cfms(P[q][c], g[q], v);
+        }
+        // the pivot column slot takes -U[s] / pivot, or 1 in the pivot row
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            P[q][s] = pr[q] ? make_double2(1.0, 0.0) : make_double2(-g[q].x, -g[q].y);
+        if (tid == 0) piv[s] = gr < 0 ? 0 : gr;
+        if (next) publish(sb ^ 1);
+    };
+    [&]<int... S>(std::integer_sequence<int, S...>) {
+        (column(std::integral_constant<int, S>{}), ...);
+    }(std::make_integer_sequence<int, NB>{});
     if (bad && tid == 0 && atomicCAS(&status->code, 0, 3) == 0) status->tag = J.tag;
     __syncthreads();
+
+    // write back block p (rows scaled by sc) and Mm_p = block p minus the
+    // pivot unit entries
     double2* Mm = J.Mm + (size_t)(p & 1) * d * NB;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -331,8 +370,8 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 if (c < nc) {
-                    row[c] = P[q][c];
-                    double2 v = P[q][c];
+                    double2 v = cmul_i(sc[q], P[q][c]);
+                    row[c] = v;
                     if (piv[c] == r) v.x -= 1.0;
                     mrow[c] = v;
                 } else {
