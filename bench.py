@@ -57,6 +57,25 @@ def time_solves(torch, sol, dA, dB, XR, XL, steps, warmup):
     return t1 - t0, lat
 
 
+def measured_traffic(kernel, workload, partitions):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
+    against a plain copy) as last measured with rocprofv3 counters, or None if
+    there is no measurement for this workload or the kernel source changed since."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, "profiles", "traffic.json")) as f:
+            rec = json.load(f).get(kernel)
+        if not rec or rec["workload"] != workload or rec["partitions"] != partitions:
+            return None
+        with open(os.path.join(root, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def cpu_baseline(A, B, seconds, XR_gpu, XL_gpu):
     """The oracle (sequential RGF, NumPy complex128) on the host cores, bounded sample."""
     import numpy as np
@@ -330,9 +349,12 @@ def main():
         achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    roof["traffic"] = measured_traffic(dom_name, cfg.name, P)
     roof["kernel"] = dom_name
     roof["launches_per_solve"] = dom["launches"] / args.profile_steps
     roof["avg_launch_us"] = round(per_launch_ms * 1e3, 2)
+    roof["algorithmic_bytes_per_launch"] = round(dom["bytes"] / dom["launches"])
+    roof["algorithmic_flops_per_launch"] = round(dom["flops"] / dom["launches"])
     kernel_share = {k: round(v["total_ms"] / args.profile_steps, 3) for k, v in stats.items()}
     log(f"[bench] P={P} per-solve kernel ms: {kernel_share}")
     sol.destroy()
