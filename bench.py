@@ -132,13 +132,15 @@ def bench_batch(args, torch, S):
     torch.cuda.synchronize()
     flops = sum(S.flops(sp["n"], sp["b"], sp["a"], 1)[0] for sp in specs)
 
-    def run_batched(precision, waves):
+    def run_batched(precision, waves, router=None):
         out = {}
         t_total = 0.0
         errs, fbs = [], []
         for w0 in range(0, len(specs), waves):
             sub = list(range(w0, min(len(specs), w0 + waves)))
-            wspecs = [dict(n=specs[i]["n"], b=specs[i]["b"], a=specs[i]["a"], precision=precision) for i in sub]
+            precs = [router.choose(specs[i]["b"], specs[i]["a"]) if router else precision for i in sub]
+            wspecs = [dict(n=specs[i]["n"], b=specs[i]["b"], a=specs[i]["a"], precision=pr)
+                      for i, pr in zip(sub, precs)]
             XR = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
             XL = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
             bs = S.BatchSolver(wspecs)
@@ -154,6 +156,10 @@ def bench_batch(args, torch, S):
             t_total += time.perf_counter() - t0
             errs += e
             fbs += f
+            if router:
+                for i, pr, fb in zip(sub, precs, f):
+                    if pr == S.BT_MIXED:
+                        router.record(specs[i]["b"], specs[i]["a"], fb)
             bs.destroy()
             del XR, XL
         out["solves_per_s"] = round(len(specs) / t_total, 3)
@@ -162,10 +168,15 @@ def bench_batch(args, torch, S):
         if precision == S.BT_MIXED:
             out["max_err_estimate"] = max(errs)
             out["fp64_fallbacks"] = int(sum(fbs))
+        if router:
+            out["routed_to_fp64"] = router.routed
         return out
 
-    mixed = run_batched(S.BT_MIXED, args.batch_wave)
-    log(f"[bench] mixed batched: {mixed}")
+    from paper_2601_04904_amd.serving import PrecisionRouter
+    mixed_spec = run_batched(S.BT_MIXED, args.batch_wave)
+    log(f"[bench] mixed batched, every instance tried in mixed precision: {mixed_spec}")
+    mixed = run_batched(S.BT_MIXED, args.batch_wave, router=PrecisionRouter())
+    log(f"[bench] mixed batched with precision routing: {mixed}")
     fp64 = run_batched(S.BT_FP64, args.batch_wave)
     log(f"[bench] fp64 batched: {fp64}")
     # plain RGF: FP64, one instance at a time, one launch per block product, one stream
@@ -193,7 +204,7 @@ def bench_batch(args, torch, S):
         "data": "synthetic",
         "config": {"workload": f"batch_{len(specs)}_uneven", "n": "U{16..96}", "b": "U{64..384}",
                    "a": "U{0,128,256}", "eta": 1e-3, "wave": args.batch_wave},
-        "mixed_batched": mixed, "fp64_batched": fp64, "plain_rgf": plain,
+        "mixed_batched": mixed, "mixed_batched_no_routing": mixed_spec, "fp64_batched": fp64, "plain_rgf": plain,
         "mixed_vs_plain_rgf": round(mixed["solves_per_s"] / plain["solves_per_s"], 3),
         "pct_fp32_peak_mixed_executed": round(100 * mixed["tflops_executed"] / FP32_PEAK_TFLOPS, 2),
         "pct_fp64_peak_fp64_executed": round(100 * fp64["tflops_executed"] / FP64_PEAK_TFLOPS, 2),
@@ -209,10 +220,13 @@ def bench_serve(args, torch, S):
                           n_range=(16, args.serve_max_n), b_choices=tuple(range(128, args.serve_max_b + 1, 64)))
     reqs = serving.requests_from_trace(trace)
     budget = int(args.serve_budget_gb * 1e9)
-    eng = serving.ServingEngine(budget_bytes=budget, max_inflight=args.inflight, max_wave=args.max_wave)
+    eng = serving.ServingEngine(budget_bytes=budget, max_inflight=args.inflight, max_wave=args.max_wave,
+                                router=serving.PrecisionRouter())
     stats = eng.replay(reqs)
     stats["waves"] = eng.waves
     stats["errors"] = eng.errors
+    stats["routed_to_fp64"] = eng.router.routed
+    stats["oom_retries"] = eng.oom_retries
     log(f"[bench] serving: {stats}")
     # plain RGF on the same trace: FP64 only, one request at a time, one launch per product
     plain_reqs = serving.requests_from_trace(trace)

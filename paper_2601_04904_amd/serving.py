@@ -47,11 +47,14 @@ class Request:
     fallback: list = field(default_factory=list)
     keep_outputs: bool = False
     outputs: object = None
+    run_precision: int = -1            # precision actually run (set by the router), -1: as asked
 
     def spec(self):
+        prec = S.BT_MIXED if self.precision == "mixed" else S.BT_FP64
+        if self.run_precision >= 0:
+            prec = self.run_precision
         return dict(n=self.n, b=self.b, a=self.a, partitions=self.partitions,
-                    precision=S.BT_MIXED if self.precision == "mixed" else S.BT_FP64,
-                    tol=1e-4, flags=self.flags)
+                    precision=prec, tol=1e-4, flags=self.flags)
 
     def pattern_elems(self):
         n, b, a = self.n, self.b, self.a
@@ -66,12 +69,54 @@ class Request:
 def request_footprint(req: Request) -> int:
     ws = S.batch_workspace_bytes([req.spec()])
     io = 16 * req.pattern_elems() * (4 + 2 * (req.nrhs - 1))   # A, B, XR, XL (+ B2, XL2)
-    return ws + io
+    gen = 16 * 3 * req.n * req.b * req.b                         # transient blocks of the input generator
+    return ws + io + gen
+
+
+class PrecisionRouter:
+    """Routes requests that ask for the mixed path.
+
+    The mixed path runs its bulk products in complex64 and re-runs an instance
+    in FP64 when its error estimate exceeds the tolerance, so on inputs whose
+    conditioning amplifies FP32 rounding past the tolerance it costs a mixed
+    run plus an FP64 run.  The router keeps, per shape class (block size and
+    whether there is an arrowhead), a running fallback rate of the mixed runs
+    it has seen; once that rate is above `threshold` (after `probe` runs),
+    further mixed requests of the class go straight to FP64, except every
+    `reprobe`-th one, which still tries the mixed path so the rate can recover.
+    """
+
+    def __init__(self, threshold: float = 0.5, probe: int = 2, reprobe: int = 16, decay: float = 0.8):
+        self.threshold, self.probe, self.reprobe, self.decay = threshold, probe, reprobe, decay
+        self.rate = {}
+        self.seen = {}
+        self.routed = 0
+        self.lock = threading.Lock()
+
+    @staticmethod
+    def key(b: int, a: int):
+        return (b, a > 0)
+
+    def choose(self, b: int, a: int) -> int:
+        k = self.key(b, a)
+        with self.lock:
+            n = self.seen.get(k, 0)
+            self.seen[k] = n + 1
+            if n < self.probe or self.rate.get(k, 0.0) <= self.threshold or n % self.reprobe == 0:
+                return S.BT_MIXED
+            self.routed += 1
+            return S.BT_FP64
+
+    def record(self, b: int, a: int, fell_back: bool):
+        k = self.key(b, a)
+        with self.lock:
+            r = self.rate.get(k, float(fell_back))
+            self.rate[k] = self.decay * r + (1.0 - self.decay) * float(fell_back)
 
 
 class ServingEngine:
     def __init__(self, budget_bytes: int, max_inflight: int = 2, max_wave: int = 16,
-                 input_fn=None):
+                 input_fn=None, router: PrecisionRouter | None = None):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -88,6 +133,8 @@ class ServingEngine:
         self.input_fn = input_fn or self._device_inputs
         self.waves = 0
         self.max_used = 0
+        self.router = router
+        self.oom_retries = 0
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -131,7 +178,11 @@ class ServingEngine:
                 inputs = [self.input_fn(r) for r in wave]
                 XR = [S.DeviceBlocks.empty(r.n, r.b, r.a) for r in wave]
                 XL = [S.DeviceBlocks.empty(r.n, r.b, r.a) for r in wave]
-                bs = S.BatchSolver([r.spec() for r in wave], stream=stream)
+                if self.router is not None:
+                    for r in wave:
+                        if r.precision == "mixed":
+                            r.run_precision = self.router.choose(r.b, r.a)
+                bs = self._batch_solver([r.spec() for r in wave], stream)
                 err, fb = bs.solve([x[0] for x in inputs], [x[1] for x in inputs], XR, XL)
                 errs = [[e] for e in err]
                 fbs = [[f] for f in fb]
@@ -146,6 +197,10 @@ class ServingEngine:
                 bs.sync()
                 t_done = self.now()
                 bs.destroy()
+                if self.router is not None:
+                    for i, r in enumerate(wave):
+                        if r.spec()["precision"] == S.BT_MIXED:
+                            self.router.record(r.b, r.a, bool(fbs[i][0]))
                 for i, r in enumerate(wave):
                     r.t_done = t_done
                     r.err = errs[i]
@@ -162,6 +217,22 @@ class ServingEngine:
                     self.done.append(r)
                 self.busy -= 1
                 self.cv.notify_all()
+
+    def _batch_solver(self, specs, stream):
+        """The library allocates its workspace outside torch's caching allocator,
+        so blocks that torch has cached (the input generator's temporaries) are
+        released first; an allocation failure is retried once after that."""
+        torch = self.torch
+        torch.cuda.empty_cache()
+        try:
+            return S.BatchSolver(specs, stream=stream)
+        except S.BTError as ex:
+            if "OOM" not in str(ex):
+                raise
+            self.oom_retries += 1
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            return S.BatchSolver(specs, stream=stream)
 
     def dispatch(self) -> bool:
         """Start a wave if a worker is free and requests fit; returns True if one started."""
