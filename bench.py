@@ -139,7 +139,7 @@ def bench_batch(args, torch, S):
         for w0 in range(0, len(specs), waves):
             sub = list(range(w0, min(len(specs), w0 + waves)))
             precs = [router.choose(specs[i]["b"], specs[i]["a"]) if router else precision for i in sub]
-            wspecs = [dict(n=specs[i]["n"], b=specs[i]["b"], a=specs[i]["a"], precision=pr)
+            wspecs = [dict(n=specs[i]["n"], b=specs[i]["b"], a=specs[i]["a"], precision=pr, flags=args.flags)
                       for i, pr in zip(sub, precs)]
             XR = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
             XL = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
@@ -203,7 +203,8 @@ def bench_batch(args, torch, S):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
         "data": "synthetic",
         "config": {"workload": f"batch_{len(specs)}_uneven", "n": "U{16..96}", "b": "U{64..384}",
-                   "a": "U{0,128,256}", "eta": 1e-3, "wave": args.batch_wave},
+                   "a": "U{0,128,256}", "eta": 1e-3, "wave": args.batch_wave, "hip_graph": bool(args.graph),
+                   "tile_shapes": "autotuned" if args.tuned else "default rule"},
         "mixed_batched": mixed, "mixed_batched_no_routing": mixed_spec, "fp64_batched": fp64, "plain_rgf": plain,
         "mixed_vs_plain_rgf": round(mixed["solves_per_s"] / plain["solves_per_s"], 3),
         "pct_fp32_peak_mixed_executed": round(100 * mixed["tflops_executed"] / FP32_PEAK_TFLOPS, 2),
@@ -265,6 +266,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: run each solve's launch list as a captured HIP graph (BT_GRAPH)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: pick product tile shapes with the autotuner before timing")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-wave", type=int, default=32)
     ap.add_argument("--plain-count", type=int, default=8)
@@ -305,6 +310,13 @@ def main():
         print(json.dumps({"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
                           "copies": 3, "GB_per_s": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
         return
+    tuned = None
+    if args.autotune and args.workload != "copy":
+        t0 = time.perf_counter()
+        tuned = S.autotune()
+        log(f"[bench] autotuned {len(tuned)} product launch classes in {time.perf_counter() - t0:.1f} s")
+    args.flags = S.BT_GRAPH if args.graph else 0
+    args.tuned = tuned
     if args.workload == "batch":
         return bench_batch(args, torch, S)
     if args.workload == "serve":
@@ -324,7 +336,7 @@ def main():
 
     timed = {}
     for P in forms + extra:
-        sol = S.Solver(n, b, a, partitions=P)
+        sol = S.Solver(n, b, a, partitions=P, flags=args.flags)
         el, lt = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
         exP, usP = S.flops(n, b, a, P)
         timed[P] = dict(elapsed=el, lat=lt, launches=sol.last_launch_count(), ex=exP, us=usP)
@@ -409,7 +421,8 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": cfg.name, "n": n, "b": b, "a": a, "partitions": P,
-                   "E": cfg.E, "eta": cfg.eta, "seed": cfg.seed},
+                   "E": cfg.E, "eta": cfg.eta, "seed": cfg.seed, "hip_graph": bool(args.graph),
+                   "tile_shapes": "autotuned" if args.tuned else "default rule"},
         "tflops_executed": round(tflops_ex, 3),
         "tflops_useful": round(tflops_us, 3),
         "pct_fp64_peak_executed": round(100 * tflops_ex / FP64_PEAK_TFLOPS, 2),

@@ -83,6 +83,10 @@ typedef enum {
 #define BT_PLAIN 0x2u       /* reference schedule: one launch per single-term block product
                                and per inverse, in program order, on one stream (no
                                grouping, no multi-term fusion, no stream overlap) */
+#define BT_GRAPH 0x4u       /* run each compiled launch list as one captured HIP graph
+                               (captured at its first run, replayed afterwards; not while
+                               profiling).  A batch handle uses graphs when every instance
+                               sets the flag. */
 
 typedef struct {
     int32_t n;                  /* number of diagonal blocks, >= 1 */
@@ -237,6 +241,41 @@ bt_status bt_si_sq_profile(bt_si_sq_handle h, int32_t enable);
  * family that ran) into out and their number into *count. */
 bt_status bt_si_sq_profile_stats(bt_si_sq_handle h, bt_kernel_stat* out, int32_t max_entries,
                                  int32_t* count);
+
+/* ---- Tile-shape tuning of the grouped complex products -------------------
+ *
+ * Every block update of the sweeps is a dense complex product (Sec. II-B,
+ * the products of Alg. 1 and Alg. 2 and their arrowhead and partitioned
+ * forms); one launch runs all products of one dependency level.  The
+ * product kernel has BT_TILE_SHAPES tile shapes (complex rows x columns):
+ * 0 = 32 x 32, 1 = 64 x 32, 2 = 64 x 64.  A launch is classified by
+ * precision (0 FP64, 1 mixed), size class (log2 of its largest output
+ * dimension, 32..1024 -> 0..5) and work class (log2 of its 64 x 32 tile
+ * count, 1..8192 -> 0..13); the shape of a class comes from a process-wide
+ * tuning table, or from a default rule for classes never tuned.  Handles
+ * compile their launch lists when a pointer set is first used, so a table
+ * change reaches launch lists compiled after it. */
+#define BT_TILE_SHAPES 3
+#define BT_TUNE_SIZE_CLASSES 6
+#define BT_TUNE_WORK_CLASSES 14
+#define BT_TUNE_ENTRIES (2 * BT_TUNE_SIZE_CLASSES * BT_TUNE_WORK_CLASSES)
+
+/* Times every tile shape on synthetic grouped launches of square products
+ * (sizes 64..1024, 1 to 4096 products per launch) in both precisions and
+ * stores the fastest shape of each class reached into the tuning table.
+ * Allocates and frees its own device scratch (about 300 MB), runs on
+ * hip_stream (NULL: the null stream) and returns when done (a few seconds).
+ * If report is not NULL, a text line per class ("prec size_class work_class
+ * shape us_shape0 us_shape1 us_shape2") is written into it (truncated to cap
+ * bytes, NUL-terminated).
+ * Errors: BT_ERR_OOM, BT_ERR_HIP (the table is left unchanged). */
+bt_status bt_si_sq_autotune(void* hip_stream, char* report, size_t cap);
+
+/* Reads (get != 0) or writes (get == 0) the tuning table: table holds
+ * BT_TUNE_ENTRIES int32 values laid out [precision][size class][work class],
+ * each a tile shape or -1 (untuned: default rule).  Writing rejects values
+ * outside [-1, BT_TILE_SHAPES) with BT_ERR_INVALID and changes nothing. */
+bt_status bt_si_sq_tune_table(int32_t* table, int32_t get);
 
 #ifdef __cplusplus
 }

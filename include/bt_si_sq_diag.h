@@ -18,12 +18,13 @@ extern "C" {
  * opA/opB: 0 = as stored, 1 = conjugate transpose (then A is stored k x m,
  * B is stored n x k).  alpha, beta: host arrays {re, im}.  C may be NULL
  * (beta ignored) or equal D.  mixed = 1 runs the product in complex64 on
- * FP32 MFMA (the mixed-precision path). */
+ * FP32 MFMA (the mixed-precision path).  shape: tile shape 0..BT_TILE_SHAPES-1,
+ * or -1 for the one the tuning table gives this launch. */
 bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
                              const double* alpha, const void* A, int32_t lda, int32_t opA,
                              const void* B, int32_t ldb, int32_t opB,
                              const double* beta, const void* C, int32_t ldc,
-                             void* D, int32_t ldd, int32_t mixed, void* hip_stream);
+                             void* D, int32_t ldd, int32_t mixed, int32_t shape, void* hip_stream);
 
 /* dst[i] = src[i]^-1 for `count` contiguous d x d matrices (Gauss-Jordan with
  * partial pivoting inside each matrix, as used for the diagonal Schur

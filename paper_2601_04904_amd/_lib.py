@@ -9,9 +9,14 @@ LIB_PATH = os.path.join(HERE, "libbtsisq.so")
 
 BT_OK, BT_ERR_INVALID, BT_ERR_OOM, BT_ERR_SINGULAR, BT_ERR_HIP, BT_ERR_STATE, BT_ERR_TOLERANCE = range(7)
 BT_FP64, BT_MIXED = 0, 1
-BT_DIAG_ONLY, BT_PLAIN = 0x1, 0x2
+BT_DIAG_ONLY, BT_PLAIN, BT_GRAPH = 0x1, 0x2, 0x4
 STATUS_NAMES = {0: "BT_OK", 1: "BT_ERR_INVALID", 2: "BT_ERR_OOM", 3: "BT_ERR_SINGULAR",
                 4: "BT_ERR_HIP", 5: "BT_ERR_STATE", 6: "BT_ERR_TOLERANCE"}
+
+BT_TILE_SHAPES = 3
+BT_TUNE_SIZE_CLASSES = 6
+BT_TUNE_WORK_CLASSES = 14
+BT_TUNE_ENTRIES = 2 * BT_TUNE_SIZE_CLASSES * BT_TUNE_WORK_CLASSES
 
 EXPORTED = [
     "bt_si_sq_workspace_bytes", "bt_si_sq_partition_bounds", "bt_si_sq_flops",
@@ -20,6 +25,7 @@ EXPORTED = [
     "bt_si_sq_profile", "bt_si_sq_profile_stats",
     "bt_si_sq_batch_workspace_bytes", "bt_si_sq_batch_create", "bt_si_sq_batch_solve",
     "bt_si_sq_batch_count", "bt_si_sq_batch_selected_solve",
+    "bt_si_sq_autotune", "bt_si_sq_tune_table",
     "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse", "bt_si_sq_diag_schedule",
 ]
 
@@ -104,10 +110,15 @@ def lib():
     L.bt_si_sq_batch_selected_solve.restype = C.c_int
     L.bt_si_sq_batch_count.argtypes = [H]
     L.bt_si_sq_batch_count.restype = C.c_int32
+    L.bt_si_sq_autotune.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
+    L.bt_si_sq_autotune.restype = C.c_int
+    L.bt_si_sq_tune_table.argtypes = [C.POINTER(C.c_int32), C.c_int32]
+    L.bt_si_sq_tune_table.restype = C.c_int
     dp = C.POINTER(C.c_double)
     L.bt_si_sq_diag_gemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_void_p, C.c_int32,
                                      C.c_int32, C.c_void_p, C.c_int32, C.c_int32, dp, C.c_void_p,
-                                     C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+                                     C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_void_p]
     L.bt_si_sq_diag_gemm.restype = C.c_int
     L.bt_si_sq_diag_inverse.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_int32), C.c_void_p]

@@ -17,6 +17,7 @@ struct GemmTerm {
 };
 
 constexpr int kMaxTerms = 6;
+constexpr int kGemmShapes = 3;     // product tile shapes: 32x32, 64x32, 64x64 complex
 constexpr int kTermAH = 1;
 constexpr int kTermBH = 2;
 

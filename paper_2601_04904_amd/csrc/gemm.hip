@@ -25,8 +25,6 @@ namespace btsq {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 64;          // complex rows per tile
-constexpr int kBN = 32;          // complex columns per tile (64 real)
 constexpr int kBK = 16;          // complex k per LDS stage
 constexpr int kThreads = 256;    // 4 waves, 2 x 2 over the tile
 
@@ -92,12 +90,12 @@ typedef const double2* gptr_t;
 
 // Raw operands of one stage in flight: values, in-range flags and the term's
 // op / alpha needed to finish them.
-template <int BM>
+template <int BM, int BN>
 struct Stage {
     double2 ra[BM * kBK / kThreads];
-    double2 rb[kBN * kBK / kThreads];
+    double2 rb[BN * kBK / kThreads];
     bool oka[BM * kBK / kThreads];
-    bool okb[kBN * kBK / kThreads];
+    bool okb[BN * kBK / kThreads];
     bool ah, bh;
     double2 alpha;
 };
@@ -106,11 +104,11 @@ struct Stage {
 // unconditional (indices clamped into the matrix; out-of-range values are
 // replaced by zero in finish_stage) so that they are all in flight together
 // and overlap the MFMAs of the current stage.
-template <int BM>
+template <int BM, int BN>
 __device__ inline void issue_stage(const GemmTerm& T, int m, int n, int i0, int j0, int k0,
-                                   int tid, Stage<BM>& st) {
+                                   int tid, Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
-    constexpr int NB = kBN * kBK / kThreads;
+    constexpr int NB = BN * kBK / kThreads;
     const bool ah = T.flags & kTermAH;
     const bool bh = T.flags & kTermBH;
     st.ah = ah;
@@ -133,8 +131,8 @@ __device__ inline void issue_stage(const GemmTerm& T, int m, int n, int i0, int 
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int e = tid + kThreads * q;
-        const int j = bh ? (e / kBK) : (e % kBN);
-        const int p = bh ? (e % kBK) : (e / kBN);
+        const int j = bh ? (e / kBK) : (e % BN);
+        const int p = bh ? (e % kBK) : (e / BN);
         const int gj = j0 + j, gp = k0 + p;
         st.okb[q] = gj < n && gp <= km1;
         const int gjc = min(gj, n - 1), gpc = min(gp, km1);
@@ -146,10 +144,10 @@ __device__ inline void issue_stage(const GemmTerm& T, int m, int n, int i0, int 
 // Conjugate, scale by alpha and zero the out-of-range values.  The empty asm
 // consumes every loaded value, so the compiler cannot turn the loads back
 // into conditional ones.
-template <int BM>
-__device__ inline void finish_stage(Stage<BM>& st) {
+template <int BM, int BN>
+__device__ inline void finish_stage(Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
-    constexpr int NB = kBN * kBK / kThreads;
+    constexpr int NB = BN * kBK / kThreads;
 #pragma unroll
     for (int q = 0; q < NA; ++q) asm volatile("" : "+v"(st.ra[q].x), "+v"(st.ra[q].y));
 #pragma unroll
@@ -169,12 +167,12 @@ __device__ inline void finish_stage(Stage<BM>& st) {
     }
 }
 
-template <bool MIXED, int BM>
-__device__ inline void store_stage(int tid, const Stage<BM>& st,
+template <bool MIXED, int BM, int BN>
+__device__ inline void store_stage(int tid, const Stage<BM, BN>& st,
                                    typename Prec<MIXED>::C (*As)[BM + 1],
-                                   typename Prec<MIXED>::C (*Bs)[kBN + 1]) {
+                                   typename Prec<MIXED>::C (*Bs)[BN + 1]) {
     constexpr int NA = BM * kBK / kThreads;
-    constexpr int NB = kBN * kBK / kThreads;
+    constexpr int NB = BN * kBK / kThreads;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         const int e = tid + kThreads * q;
@@ -185,23 +183,25 @@ __device__ inline void store_stage(int tid, const Stage<BM>& st,
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int e = tid + kThreads * q;
-        const int j = st.bh ? (e / kBK) : (e % kBN);
-        const int p = st.bh ? (e % kBK) : (e / kBN);
+        const int j = st.bh ? (e / kBK) : (e % BN);
+        const int p = st.bh ? (e % kBK) : (e / BN);
         Bs[p][j] = Prec<MIXED>::cvt(st.rb[q]);
     }
 }
 
-// One workgroup computes a BM x kBN complex tile; its 4 waves split the tile
-// 2 x 2 (BM/2 rows x 32 real columns each, i.e. MI x 2 MFMA blocks).
-template <bool MIXED, int BM>
+// One workgroup computes a BM x BN complex tile; its 4 waves split the tile
+// 2 x 2 (BM/2 rows x BN real columns each, i.e. row groups x BN/16 MFMA
+// column blocks).
+template <bool MIXED, int BM, int BN>
 __global__ __launch_bounds__(kThreads)
 void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     typedef typename Prec<MIXED>::C CT;
     typedef typename Prec<MIXED>::R RT;
     typedef typename Prec<MIXED>::Acc AccT;
     constexpr int MI = BM / 32;
+    constexpr int NI = BN / 16;
     __shared__ CT As[2][kBK][BM + 1];
-    __shared__ CT Bs[2][kBK][kBN + 1];
+    __shared__ CT Bs[2][kBK][BN + 1];
     __shared__ GemmTerm terms[kMaxTerms];
 
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -209,7 +209,7 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     const int m = op->m, n = op->n, nterms = op->nterms;
     const int local = bid - op->tile_begin;
     const int tm = local / op->tiles_n, tn = local - tm * op->tiles_n;
-    const int i0 = tm * BM, j0 = tn * kBN;
+    const int i0 = tm * BM, j0 = tn * BN;
     const int tid = threadIdx.x;
     if (tid < nterms) terms[tid] = op->t[tid];
     __syncthreads();
@@ -228,33 +228,33 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     // measured on gfx950).  A wave covers BM/2 rows as RG groups of 4 rows.
     // FP32 (mixed): v_mfma_f32_16x16x4f32, MI blocks of 16 rows.
     constexpr int RG = MIXED ? MI : BM / 8;
-    AccT acc[RG][2];
+    AccT acc[RG][NI];
 #pragma unroll
     for (int a = 0; a < RG; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NI; ++b)
             acc[a][b] = AccT{};
 
     int t = 0, k0 = 0;
     while (t < nterms && terms[t].k <= 0) ++t;
-    Stage<BM> st;
+    Stage<BM, BN> st;
     int buf = 0;
     if (t < nterms) {
-        issue_stage<BM>(terms[t], m, n, i0, j0, k0, tid, st);
-        finish_stage<BM>(st);
-        store_stage<MIXED, BM>(tid, st, As[0], Bs[0]);
+        issue_stage<BM, BN>(terms[t], m, n, i0, j0, k0, tid, st);
+        finish_stage<BM, BN>(st);
+        store_stage<MIXED, BM, BN>(tid, st, As[0], Bs[0]);
     }
     __syncthreads();
     while (t < nterms) {
         int tn2 = t, kn = k0 + kBK;
         while (tn2 < nterms && kn >= terms[tn2].k) { ++tn2; kn = 0; }
         const bool has_next = tn2 < nterms;
-        if (has_next) issue_stage<BM>(terms[tn2], m, n, i0, j0, kn, tid, st);
+        if (has_next) issue_stage<BM, BN>(terms[tn2], m, n, i0, j0, kn, tid, st);
 
 #pragma unroll
         for (int kk = 0; kk < kBK / 2; ++kk) {
             const int p = 2 * kk + pOff;
-            RT av[RG], bv[2];
+            RT av[RG], bv[NI];
             // one component read per operand: A' takes component cA, B'' takes
             // component cA ^ d, negated for (cA, d) = (1, 0)
 #pragma unroll
@@ -263,20 +263,20 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
                 av[g] = reinterpret_cast<const RT*>(&As[buf][p][row])[cA];
             }
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) {
-                const int jc = (wn * 32 + ni * 16 + r16) >> 1;
+            for (int ni = 0; ni < NI; ++ni) {
+                const int jc = (wn * BN + ni * 16 + r16) >> 1;
                 const RT v = reinterpret_cast<const RT*>(&Bs[buf][p][jc])[cA ^ d];
                 bv[ni] = Prec<MIXED>::flip(v, negB);
             }
 #pragma unroll
             for (int g = 0; g < RG; ++g)
 #pragma unroll
-                for (int ni = 0; ni < 2; ++ni)
+                for (int ni = 0; ni < NI; ++ni)
                     acc[g][ni] = Prec<MIXED>::mfma(av[g], bv[ni], acc[g][ni]);
         }
         if (has_next) {
-            finish_stage<BM>(st);
-            store_stage<MIXED, BM>(tid, st, As[buf ^ 1], Bs[buf ^ 1]);
+            finish_stage<BM, BN>(st);
+            store_stage<MIXED, BM, BN>(tid, st, As[buf ^ 1], Bs[buf ^ 1]);
         }
         __syncthreads();
         buf ^= 1;
@@ -294,33 +294,33 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     const double2 beta = op->beta;
     if (C) {
         // all C loads first (clamped, unconditional), then the stores
-        double2 cv[RG][2][NR];
+        double2 cv[RG][NI][NR];
         const gptr_t Cp = (gptr_t)C;
 #pragma unroll
         for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     const int row = min(i0 + wm * (BM / 2) + g * GR + Prec<MIXED>::row_of(lane, r), m - 1);
-                    const int col = min(j0 + ((wn * 32 + ni * 16 + r16) >> 1), n - 1);
+                    const int col = min(j0 + ((wn * BN + ni * 16 + r16) >> 1), n - 1);
                     cv[g][ni][r] = Cp[(size_t)row * ldc + col];
                 }
 #pragma unroll
         for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
                     asm volatile("" : "+v"(cv[g][ni][r].x), "+v"(cv[g][ni][r].y));
 #pragma unroll
         for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     const int row = i0 + wm * (BM / 2) + g * GR + Prec<MIXED>::row_of(lane, r);
-                    const int col = j0 + ((wn * 32 + ni * 16 + r16) >> 1);
+                    const int col = j0 + ((wn * BN + ni * 16 + r16) >> 1);
                     const double2 c = cv[g][ni][r];
                     const double v = Prec<MIXED>::elem(acc[g][ni], r) +
                         (d ? (beta.x * c.y + beta.y * c.x) : (beta.x * c.x - beta.y * c.y));
@@ -330,45 +330,43 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
 #pragma unroll
         for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+            for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     const int row = i0 + wm * (BM / 2) + g * GR + Prec<MIXED>::row_of(lane, r);
-                    const int col = j0 + ((wn * 32 + ni * 16 + r16) >> 1);
+                    const int col = j0 + ((wn * BN + ni * 16 + r16) >> 1);
                     if (row < m && col < n) D[2 * ((size_t)row * ldd + col) + d] = Prec<MIXED>::elem(acc[g][ni], r);
                 }
     }
 }
 
-// Tiles are counted in 64-row units by the scheduler; a launch whose
-// products give too few of them to fill the chip runs 32-row tiles instead
-// (twice as many workgroups).  tile_begin offsets are then doubled per op.
-int gemm_tiles(int m, int n) {
-    return ((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN);
-}
-int gemm_tiles_n(int n) { return (n + kBN - 1) / kBN; }
+// Tile shapes of the grouped product (complex rows x complex columns).
+// Every op of a launch is tiled with the launch's shape: tiles_n and
+// tile_begin of the ops must be computed with gemm_tiles_shape().
+struct TileShape { int bm, bn; };
+constexpr TileShape kShapes[kGemmShapes] = {{32, 32}, {64, 32}, {64, 64}};
 
-hipError_t launch_gemm(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s) {
+int gemm_shape_bm(int shape) { return kShapes[shape].bm; }
+int gemm_shape_bn(int shape) { return kShapes[shape].bn; }
+int gemm_tiles_shape(int m, int n, int shape) {
+    return ((m + kShapes[shape].bm - 1) / kShapes[shape].bm) * ((n + kShapes[shape].bn - 1) / kShapes[shape].bn);
+}
+int gemm_tiles_n_shape(int n, int shape) { return (n + kShapes[shape].bn - 1) / kShapes[shape].bn; }
+
+template <bool MIXED>
+static void launch_mixed(const GemmOp* d_ops, int nops, int total_tiles, int shape, hipStream_t s) {
+    switch (shape) {
+        case 0: hipLaunchKernelGGL((zgemm_grouped<MIXED, 32, 32>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops); break;
+        case 1: hipLaunchKernelGGL((zgemm_grouped<MIXED, 64, 32>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops); break;
+        default: hipLaunchKernelGGL((zgemm_grouped<MIXED, 64, 64>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops); break;
+    }
+}
+
+hipError_t launch_gemm_shape(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, int shape, hipStream_t s) {
     if (nops <= 0 || total_tiles <= 0) return hipSuccess;
-    if (mixed)
-        hipLaunchKernelGGL((zgemm_grouped<true, 64>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
-    else
-        hipLaunchKernelGGL((zgemm_grouped<false, 64>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
-    return hipGetLastError();
-}
-
-// Same with 32-row tiles; tile_begin / tile counts of the ops must be in
-// 32-row units (gemm_tiles32).
-int gemm_tiles32(int m, int n) {
-    return ((m + 31) / 32) * ((n + kBN - 1) / kBN);
-}
-
-hipError_t launch_gemm32(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s) {
-    if (nops <= 0 || total_tiles <= 0) return hipSuccess;
-    if (mixed)
-        hipLaunchKernelGGL((zgemm_grouped<true, 32>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
-    else
-        hipLaunchKernelGGL((zgemm_grouped<false, 32>), dim3(total_tiles), dim3(kThreads), 0, s, d_ops, nops);
+    if (shape < 0 || shape >= kGemmShapes) return hipErrorInvalidValue;
+    if (mixed) launch_mixed<true>(d_ops, nops, total_tiles, shape, s);
+    else launch_mixed<false>(d_ops, nops, total_tiles, shape, s);
     return hipGetLastError();
 }
 

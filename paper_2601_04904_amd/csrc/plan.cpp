@@ -33,21 +33,23 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <atomic>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
 namespace btsq {
-hipError_t launch_gemm(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s);
-int gemm_tiles(int m, int n);
-int gemm_tiles_n(int n);
+hipError_t launch_gemm_shape(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, int shape, hipStream_t s);
+int gemm_tiles_shape(int m, int n, int shape);
+int gemm_tiles_n_shape(int n, int shape);
+int gemm_shape_bm(int shape);
+int gemm_shape_bn(int shape);
 hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
 hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
 int inv_variant(int d);   // panel kernel shape for dimension d: 0 (256 x 1 rows), 1 (256 x 2), 2 (512 x 2)
 hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int panel, int maxd,
                            DevStatus* status, hipStream_t s);
 hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s);
-hipError_t launch_gemm32(const GemmOp* d_ops, int nops, int total_tiles, bool mixed, hipStream_t s);
-int gemm_tiles32(int m, int n);
 hipError_t launch_norms(const NormJob* d_jobs, int njobs, hipStream_t s);
 }  // namespace btsq
 
@@ -668,7 +670,7 @@ struct Launch {
     size_t maxelems;  // add
     double flops = 0; // algorithmic work of the launch
     double bytes = 0;
-    int bm = 64;      // gemm: tile rows
+    int shape = 1;    // gemm: tile shape (gemm_shape_bm / gemm_shape_bn)
     int cls = 0;      // stream class
     int level = 0;
     int wait_level = -1;  // wait for the other stream up to this level
@@ -676,8 +678,6 @@ struct Launch {
     int rec_event = -1;   // event slot to record after the launch
 };
 
-// Launches with fewer 64-row tiles than this run 32-row tiles.
-constexpr int kSmallLaunchTiles = 512;
 
 // Algorithmic flops and HBM bytes of a grouped product launch.
 void gemm_work(const GemmOp* ops, int n, double& flops, double& bytes) {
@@ -716,7 +716,6 @@ GemmOp make_gemm_op(const OpRec& o) {
     g.m = o.D.r;
     g.n = o.D.c;
     g.nterms = (int)o.terms.size();
-    g.tiles_n = gemm_tiles_n(g.n);
     g.mixed = o.mixed ? 1 : 0;
     g.beta = o.beta;
     for (size_t i = 0; i < o.terms.size(); ++i) {
@@ -733,17 +732,59 @@ GemmOp make_gemm_op(const OpRec& o) {
     return g;
 }
 
-// Retile a grouped product launch with 32-row tiles when it has few tiles.
-void choose_tiles(Program& pg, Launch& L) {
-    if (L.tiles >= kSmallLaunchTiles) return;
+// Product tile shape per launch.  A launch is classified by precision, the
+// size class of its largest output (log2 of max(m, n), 5..10) and the class of
+// its work (log2 of its 64 x 32 tile count, 0..13); the shape comes from the
+// tuning table (filled by bt_si_sq_autotune or loaded with
+// bt_si_sq_tune_table) or, for classes never tuned, from the default rule:
+// 32 x 32 tiles below 512 tiles of 64 x 32, 64 x 32 tiles above.
+constexpr int kMClasses = 6, kTClasses = 14;
+std::atomic<int> g_tune[2][kMClasses][kTClasses];
+std::once_flag g_tune_once;
+
+void tune_init() {
+    std::call_once(g_tune_once, [] {
+        for (auto& a : g_tune) for (auto& b : a) for (auto& c : b) c.store(-1);
+    });
+}
+
+int log2_class(long v, int lo, int hi) {
+    int c = 0;
+    while ((1L << (c + 1)) <= v) ++c;
+    return std::min(std::max(c, lo), hi) - lo;
+}
+
+int default_shape(long tiles64x32) { return tiles64x32 < 512 ? 0 : 1; }
+
+int pick_shape(int mixed, int maxdim, long tiles64x32) {
+    tune_init();
+    const int mc = log2_class(maxdim, 5, 5 + kMClasses - 1);
+    const int tc = log2_class(std::max(1L, tiles64x32), 0, kTClasses - 1);
+    const int v = g_tune[mixed ? 1 : 0][mc][tc].load();
+    return (v >= 0 && v < kGemmShapes) ? v : default_shape(tiles64x32);
+}
+
+void set_shape(Program& pg, Launch& L, int shape) {
     int tiles = 0;
     for (int i = 0; i < L.count; ++i) {
         GemmOp& g = pg.gemm[L.off + i];
         g.tile_begin = tiles;
-        tiles += gemm_tiles32(g.m, g.n);
+        g.tiles_n = gemm_tiles_n_shape(g.n, shape);
+        tiles += gemm_tiles_shape(g.m, g.n, shape);
     }
     L.tiles = tiles;
-    L.bm = 32;
+    L.shape = shape;
+}
+
+void assign_shape(Program& pg, Launch& L) {
+    long t1 = 0;
+    int maxdim = 1;
+    for (int i = 0; i < L.count; ++i) {
+        const GemmOp& g = pg.gemm[L.off + i];
+        t1 += gemm_tiles_shape(g.m, g.n, 1);
+        maxdim = std::max(maxdim, std::max(g.m, g.n));
+    }
+    set_shape(pg, L, pick_shape(L.mixed, maxdim, t1));
 }
 
 // Turn levelled operations into typed device arrays and a launch list.
@@ -823,14 +864,13 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                     const OpRec& o = ops[i];
                     if (o.kind != K_GEMM || (int)o.mixed != mx || o.cls != cls) continue;
                     GemmOp g = make_gemm_op(o);
-                    g.tile_begin = tiles;
-                    tiles += gemm_tiles(g.m, g.n);
+                    tiles += gemm_tiles_shape(g.m, g.n, 1);
                     pg.gemm.push_back(g);
                     gw = std::max(gw, o.wait_other);
                 }
                 if (pg.gemm.size() > g0) {
                     Launch gl = mk(0, g0, (int)(pg.gemm.size() - g0), tiles, mx, 0, 0, 0, cls, L, gw);
-                    choose_tiles(pg, gl);
+                    assign_shape(pg, gl);
                     pg.launches.push_back(gl);
                 }
             }
@@ -956,6 +996,9 @@ struct bt_si_sq_plan {
     DevStatus* status = nullptr;
     std::string err;
     int32_t last_launches = 0;
+    bool use_graph = false;               // BT_GRAPH on every instance
+    hipStream_t gstream = nullptr;        // private stream graphs are captured on and replayed from
+    hipEvent_t ev_pre = nullptr, ev_post = nullptr;
     struct Cached {
         std::vector<uint64_t> key;
         uint64_t stamp = 0;
@@ -966,6 +1009,7 @@ struct bt_si_sq_plan {
         size_t dev_bytes = 0;
         size_t off_gemm = 0, off_inv = 0, off_add = 0, off_norm = 0;
         std::vector<hipEvent_t> events;   // cross-stream events of the launch list
+        hipGraphExec_t graph = nullptr;   // the launch list captured as a graph (BT_GRAPH)
     };
     std::vector<Cached> cache;            // small LRU of compiled programs
     uint64_t clock = 0;
@@ -1106,7 +1150,41 @@ int kernel_kind(const Launch& L) {
     }
 }
 
+hipError_t enqueue_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, hipStream_t main);
+
+// Run a compiled launch list: directly on the handle's stream, or (BT_GRAPH,
+// not profiling) as a HIP graph.  The graph is captured at the list's first
+// run from the same enqueue sequence on the handle's private graph stream
+// (the caller's stream may be the null stream, which cannot be captured); the
+// capture spans both streams of the sequence (the critical stream joins
+// through ev_start and rejoins through ev_end).  The sequence holds kernel
+// launches and event records/waits only: no memsets, no host copies.  A
+// replay is ordered after the work already queued on the caller's stream and
+// before anything queued there afterwards.
 hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
+    if (!h->use_graph || h->profiling) return enqueue_program(h, c, h->stream);
+    hipError_t e = hipSuccess;
+    if (!c.graph) {
+        e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        e = enqueue_program(h, c, h->gstream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->gstream, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c.graph, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        if (e != hipSuccess) { c.graph = nullptr; return e; }
+    }
+    e = hipEventRecord(h->ev_pre, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->gstream, h->ev_pre, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(c.graph, h->gstream);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_post, h->gstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_post, 0);
+    h->last_launches = (int32_t)c.prog.launches.size();
+    return e;
+}
+
+hipError_t enqueue_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, hipStream_t main) {
     const Program& pg = c.prog;
     GemmOp* dg = reinterpret_cast<GemmOp*>(c.dev + c.off_gemm);
     InvJob* dj = reinterpret_cast<InvJob*>(c.dev + c.off_inv);
@@ -1115,16 +1193,16 @@ hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
     hipError_t e = hipSuccess;
     if (h->profiling && h->ev_used + 2 * pg.launches.size() > 200000) {
         // bound the number of outstanding events: fold in what has finished
-        hipStreamSynchronize(h->stream);
+        hipStreamSynchronize(main);
         hipStreamSynchronize(h->astream);
         collect_profile(h);
     }
     // the critical stream starts after everything already queued on the main stream
-    e = hipEventRecord(h->ev_start, h->stream);
+    e = hipEventRecord(h->ev_start, main);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->astream, h->ev_start, 0);
     if (e != hipSuccess) return e;
     for (const Launch& L : pg.launches) {
-        hipStream_t s = L.cls ? h->astream : h->stream;
+        hipStream_t s = L.cls ? h->astream : main;
         if (L.wait_event >= 0) {
             e = hipStreamWaitEvent(s, c.events[L.wait_event], 0);
             if (e != hipSuccess) return e;
@@ -1136,10 +1214,7 @@ hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
             if (ea) hipEventRecord(ea, s);
         }
         switch (L.type) {
-            case 0:
-                e = L.bm == 32 ? launch_gemm32(dg + L.off, L.count, L.tiles, L.mixed != 0, s)
-                               : launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s);
-                break;
+            case 0: e = launch_gemm_shape(dg + L.off, L.count, L.tiles, L.mixed != 0, L.shape, s); break;
             case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
             case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
             case 4: e = launch_add(da + L.off, L.count, L.maxelems, s); break;
@@ -1158,7 +1233,7 @@ hipError_t run_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
     }
     // the solve is complete when the main stream is
     e = hipEventRecord(h->ev_end, h->astream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_end, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(main, h->ev_end, 0);
     h->last_launches = (int32_t)pg.launches.size();
     return e;
 }
@@ -1187,6 +1262,12 @@ void free_cached(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
         hipStreamSynchronize(h->astream);
         hipFree(c.dev);
         c.dev = nullptr;
+    }
+    if (c.graph) {
+        hipStreamSynchronize(h->stream);
+        if (h->gstream) hipStreamSynchronize(h->gstream);
+        hipGraphExecDestroy(c.graph);
+        c.graph = nullptr;
     }
     for (auto ev : c.events) hipEventDestroy(ev);
     c.events.clear();
@@ -1430,6 +1511,11 @@ bt_status create_handle(int count, const bt_desc* descs, void* hip_stream, bt_si
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->astream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_pre, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_post, hipEventDisableTiming);
+    h->use_graph = !h->inst.empty();
+    for (auto& I : h->inst) h->use_graph = h->use_graph && (I.desc.flags & BT_GRAPH);
     if (e != hipSuccess) {
         hipFree(h->ws); hipFree(h->inv_pool); hipFree(h->status);
         return hip_err(nullptr, e, "create");
@@ -1613,12 +1699,16 @@ bt_status bt_si_sq_destroy(bt_si_sq_handle h) {
     if (!h) return BT_OK;
     hipStreamSynchronize(h->stream);
     hipStreamSynchronize(h->astream);
+    if (h->gstream) hipStreamSynchronize(h->gstream);
     for (auto& c : h->cache) free_cached(h, c);
     if (h->host_stage) hipHostFree(h->host_stage);
     if (h->upload_done) hipEventDestroy(h->upload_done);
     if (h->ev_start) hipEventDestroy(h->ev_start);
     if (h->ev_end) hipEventDestroy(h->ev_end);
+    if (h->ev_pre) hipEventDestroy(h->ev_pre);
+    if (h->ev_post) hipEventDestroy(h->ev_post);
     if (h->astream) hipStreamDestroy(h->astream);
+    if (h->gstream) hipStreamDestroy(h->gstream);
     for (auto ev : h->ev_pool) hipEventDestroy(ev);
     hipFree(h->ws);
     hipFree(h->inv_pool);
@@ -1659,6 +1749,124 @@ bt_status bt_si_sq_profile_stats(bt_si_sq_handle h, bt_kernel_stat* out, int32_t
     return BT_OK;
 }
 
+bt_status bt_si_sq_tune_table(int32_t* table, int32_t get) {
+    if (!table) return set_err(nullptr, BT_ERR_INVALID, "tune_table: null table");
+    static_assert(BT_TUNE_ENTRIES == 2 * kMClasses * kTClasses, "tuning table layout");
+    static_assert(BT_TILE_SHAPES == kGemmShapes, "tile shape count");
+    tune_init();
+    if (!get) {
+        for (int i = 0; i < BT_TUNE_ENTRIES; ++i)
+            if (table[i] < -1 || table[i] >= kGemmShapes)
+                return set_err(nullptr, BT_ERR_INVALID, "tune_table: entry out of range");
+    }
+    int i = 0;
+    for (auto& a : g_tune)
+        for (auto& b : a)
+            for (auto& c : b) {
+                if (get) table[i] = c.load();
+                else c.store(table[i]);
+                ++i;
+            }
+    return BT_OK;
+}
+
+bt_status bt_si_sq_autotune(void* hip_stream, char* report, size_t cap) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    tune_init();
+    constexpr int kMaxDim = 1024, kMaxOps = 4096;
+    const size_t in_bytes = (size_t)kMaxDim * kMaxDim * sizeof(double2);
+    const size_t out_bytes = (size_t)256 << 20;
+    char* buf = nullptr;
+    GemmOp* dops = nullptr;
+    hipError_t e = hipMalloc(&buf, 2 * in_bytes + out_bytes);
+    if (e != hipSuccess) { hipGetLastError(); return set_err(nullptr, BT_ERR_OOM, "autotune: scratch allocation failed"); }
+    e = hipMalloc(&dops, kMaxOps * sizeof(GemmOp));
+    if (e != hipSuccess) { hipGetLastError(); hipFree(buf); return set_err(nullptr, BT_ERR_OOM, "autotune: op list allocation failed"); }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    if (e == hipSuccess) e = hipMemsetAsync(buf, 0, 2 * in_bytes + out_bytes, s);
+    const double2* A = reinterpret_cast<const double2*>(buf);
+    const double2* B = reinterpret_cast<const double2*>(buf + in_bytes);
+    double2* out = reinterpret_cast<double2*>(buf + 2 * in_bytes);
+    int found[2][kMClasses][kTClasses];
+    for (auto& a : found) for (auto& b : a) for (auto& c : b) c = -1;
+    std::string rep;
+    std::vector<GemmOp> ops;
+    for (int prec = 0; prec < 2 && e == hipSuccess; ++prec) {
+        for (int mc = 1; mc < kMClasses && e == hipSuccess; ++mc) {
+            const int m = 32 << mc;
+            const long tpp = gemm_tiles_shape(m, m, 1);
+            for (int tc = 0; tc < kTClasses && e == hipSuccess; ++tc) {
+                const long target = 1L << tc;
+                if (target < tpp) continue;
+                const long nops = target / tpp;
+                if (nops > kMaxOps || (size_t)nops * m * m * sizeof(double2) > out_bytes) continue;
+                ops.assign(nops, GemmOp{});
+                for (long q = 0; q < nops; ++q) {
+                    GemmOp& g = ops[q];
+                    memset(&g, 0, sizeof g);
+                    g.D = out + (size_t)q * m * m;
+                    g.ldd = m;
+                    g.m = g.n = m;
+                    g.nterms = 1;
+                    g.mixed = prec;
+                    g.t[0].A = A;
+                    g.t[0].B = B;
+                    g.t[0].lda = g.t[0].ldb = m;
+                    g.t[0].k = m;
+                    g.t[0].alpha = cplx(1.0);
+                }
+                float best_ms = 0.0f;
+                int best = -1;
+                float ms[kGemmShapes] = {0, 0, 0};
+                for (int sh = 0; sh < kGemmShapes && e == hipSuccess; ++sh) {
+                    int tiles = 0;
+                    for (auto& g : ops) {
+                        g.tile_begin = tiles;
+                        g.tiles_n = gemm_tiles_n_shape(m, sh);
+                        tiles += gemm_tiles_shape(m, m, sh);
+                    }
+                    e = hipMemcpyAsync(dops, ops.data(), ops.size() * sizeof(GemmOp), hipMemcpyHostToDevice, s);
+                    if (e == hipSuccess) e = launch_gemm_shape(dops, (int)nops, tiles, prec != 0, sh, s);   // warm-up
+                    if (e == hipSuccess) e = hipEventRecord(ev0, s);
+                    constexpr int kReps = 3;
+                    for (int r = 0; r < kReps && e == hipSuccess; ++r)
+                        e = launch_gemm_shape(dops, (int)nops, tiles, prec != 0, sh, s);
+                    if (e == hipSuccess) e = hipEventRecord(ev1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms[sh], ev0, ev1);
+                    ms[sh] /= kReps;
+                    if (e == hipSuccess && (best < 0 || ms[sh] < best_ms)) { best = sh; best_ms = ms[sh]; }
+                }
+                if (e != hipSuccess || best < 0) break;
+                found[prec][mc][tc] = best;
+                char line[160];
+                snprintf(line, sizeof line, "%d %d %d %d %.1f %.1f %.1f\n", prec, mc, tc, best,
+                         1e3 * ms[0], 1e3 * ms[1], 1e3 * ms[2]);
+                rep += line;
+            }
+        }
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(dops);
+    hipFree(buf);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_err(nullptr, e, "autotune");
+    for (int p = 0; p < 2; ++p)
+        for (int mc = 0; mc < kMClasses; ++mc)
+            for (int tc = 0; tc < kTClasses; ++tc)
+                if (found[p][mc][tc] >= 0) g_tune[p][mc][tc].store(found[p][mc][tc]);
+    if (report && cap > 0) {
+        const size_t nbytes = std::min(cap - 1, rep.size());
+        memcpy(report, rep.data(), nbytes);
+        report[nbytes] = '\0';
+    }
+    return BT_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1672,8 +1880,9 @@ bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
                              const double* alpha, const void* A, int32_t lda, int32_t opA,
                              const void* B, int32_t ldb, int32_t opB,
                              const double* beta, const void* C, int32_t ldc,
-                             void* D, int32_t ldd, int32_t mixed, void* hip_stream) {
-    if (m < 0 || n < 0 || k < 0 || !alpha || !beta || !D || (k > 0 && (!A || !B)))
+                             void* D, int32_t ldd, int32_t mixed, int32_t shape, void* hip_stream) {
+    if (m < 0 || n < 0 || k < 0 || !alpha || !beta || !D || (k > 0 && (!A || !B)) ||
+        shape < -1 || shape >= kGemmShapes)
         return set_err(nullptr, BT_ERR_INVALID, "diag_gemm: bad arguments");
     if (m == 0 || n == 0) return BT_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1686,7 +1895,8 @@ bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
     g.m = m;
     g.n = n;
     g.nterms = k > 0 ? 1 : 0;
-    g.tiles_n = gemm_tiles_n(n);
+    if (shape < 0) shape = pick_shape(mixed, std::max(m, n), gemm_tiles_shape(m, n, 1));
+    g.tiles_n = gemm_tiles_n_shape(n, shape);
     g.tile_begin = 0;
     g.mixed = mixed;
     g.beta = cplx(beta[0], beta[1]);
@@ -1701,7 +1911,7 @@ bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
     hipError_t e = hipMalloc(&dop, sizeof g);
     if (e != hipSuccess) return hip_err(nullptr, e, "hipMalloc");
     e = hipMemcpyAsync(dop, &g, sizeof g, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_gemm(dop, 1, gemm_tiles(m, n), mixed != 0, s);
+    if (e == hipSuccess) e = launch_gemm_shape(dop, 1, gemm_tiles_shape(m, n, shape), mixed != 0, shape, s);
     hipError_t e2 = hipStreamSynchronize(s);
     hipFree(dop);
     if (e != hipSuccess) return hip_err(nullptr, e, "diag_gemm launch");
@@ -1749,10 +1959,7 @@ bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t c
     for (const Launch& L : pg.launches) {
         if (e != hipSuccess) break;
         switch (L.type) {
-            case 0:
-                e = L.bm == 32 ? launch_gemm32(dg + L.off, L.count, L.tiles, L.mixed != 0, s)
-                               : launch_gemm(dg + L.off, L.count, L.tiles, L.mixed != 0, s);
-                break;
+            case 0: e = launch_gemm_shape(dg + L.off, L.count, L.tiles, L.mixed != 0, L.shape, s); break;
             case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
             case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
             case 6: e = launch_inv_step(dj + L.off, L.count, L.maxd, L.panel, L.tiles, st, s); break;
@@ -1790,7 +1997,7 @@ extern "C" size_t bt_si_sq_diag_schedule(const bt_desc* desc, char* out, size_t 
     const int nl = levelize(bd.ops);
     std::vector<int> ng(nl), nt(nl), ni(nl), na(nl), nc1(nl);
     for (auto& o : bd.ops) {
-        if (o.kind == K_GEMM) { ng[o.level]++; nt[o.level] += gemm_tiles(o.D.r, o.D.c); }
+        if (o.kind == K_GEMM) { ng[o.level]++; nt[o.level] += gemm_tiles_shape(o.D.r, o.D.c, 1); }
         else if (o.kind == K_INV) ni[o.level]++;
         else na[o.level]++;
         if (o.cls == 1) nc1[o.level]++;

@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BT_FP64, BT_MIXED, BT_PLAIN, BTError, check, make_desc
+from ._lib import BT_FP64, BT_GRAPH, BT_MIXED, BT_PLAIN, BTError, check, make_desc
 
 FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
 
@@ -237,11 +237,54 @@ def batch_workspace_bytes(specs) -> int:
 
 
 __all__ = ["DeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
-           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BTError"]
+           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BTError",
+           "autotune", "tune_table", "set_tune_table"]
 
 
-def diag_gemm(alpha, A, opA, B, opB, beta=0.0, Cin=None, D=None, mixed=False, stream=None):
-    """D = beta Cin + alpha op(A) op(B) on the device (2-D complex128 tensors); returns D."""
+def tune_table():
+    """The product tile-shape tuning table as a list of BT_TUNE_ENTRIES ints
+    ([precision][size class][work class], -1 = default rule)."""
+    t = (C.c_int32 * _lib.BT_TUNE_ENTRIES)()
+    check(_lib.lib().bt_si_sq_tune_table(t, 1))
+    return list(t)
+
+
+def set_tune_table(table):
+    vals = [int(v) for v in table]
+    if len(vals) != _lib.BT_TUNE_ENTRIES:
+        raise ValueError(f"tuning table needs {_lib.BT_TUNE_ENTRIES} entries, got {len(vals)}")
+    t = (C.c_int32 * _lib.BT_TUNE_ENTRIES)(*vals)
+    check(_lib.lib().bt_si_sq_tune_table(t, 0))
+
+
+def autotune(stream=None, cache=None):
+    """Time the product tile shapes on this device and fill the tuning table.
+
+    Returns the report lines ("prec size_class work_class shape us0 us1 us2").
+    With cache (a file path) the table is loaded from it if present, else
+    tuned and written there (JSON)."""
+    import json
+    import os
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            rec = json.load(f)
+        set_tune_table(rec["table"])
+        return rec.get("report", [])
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    buf = C.create_string_buffer(1 << 16)
+    check(_lib.lib().bt_si_sq_autotune(C.c_void_p(st.cuda_stream), buf, len(buf)))
+    report = [ln for ln in buf.value.decode().splitlines() if ln]
+    if cache:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as f:
+            json.dump({"table": tune_table(), "report": report}, f)
+    return report
+
+
+def diag_gemm(alpha, A, opA, B, opB, beta=0.0, Cin=None, D=None, mixed=False, stream=None, shape=-1):
+    """D = beta Cin + alpha op(A) op(B) on the device (2-D complex128 tensors); returns D.
+    shape: product tile shape, -1 for the tuning table's choice."""
     torch = _torch()
     m = A.shape[1] if opA else A.shape[0]
     k = A.shape[0] if opA else A.shape[1]
@@ -255,7 +298,7 @@ def diag_gemm(alpha, A, opA, B, opB, beta=0.0, Cin=None, D=None, mixed=False, st
         m, n, k, al, A.data_ptr(), A.stride(0), int(bool(opA)), B.data_ptr(), B.stride(0),
         int(bool(opB)), be, Cin.data_ptr() if Cin is not None else None,
         Cin.stride(0) if Cin is not None else 0, D.data_ptr(), D.stride(0), int(bool(mixed)),
-        C.c_void_p(st.cuda_stream)))
+        int(shape), C.c_void_p(st.cuda_stream)))
     return D
 
 

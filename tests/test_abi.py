@@ -134,3 +134,37 @@ def test_workspace_bytes_scales():
     assert 0 < w1 < w2
     # dominated by O(n b^2) block storage
     assert w2 < 40 * 64 * 512 * 512 * 16
+
+
+def test_tune_table_roundtrip_and_validation():
+    from paper_2601_04904_amd import solver as S, _lib
+    saved = S.tune_table()
+    assert len(saved) == _lib.BT_TUNE_ENTRIES
+    assert all(-1 <= v < _lib.BT_TILE_SHAPES for v in saved)
+    try:
+        t = [(i % (_lib.BT_TILE_SHAPES + 1)) - 1 for i in range(_lib.BT_TUNE_ENTRIES)]
+        S.set_tune_table(t)
+        assert S.tune_table() == t
+        bad = list(t)
+        bad[5] = _lib.BT_TILE_SHAPES
+        with pytest.raises(S.BTError):
+            S.set_tune_table(bad)
+        assert S.tune_table() == t          # a rejected write changes nothing
+        with pytest.raises(ValueError):
+            S.set_tune_table(t[:-1])
+    finally:
+        S.set_tune_table(saved)
+
+
+def test_header_flag_values_match_binding():
+    from paper_2601_04904_amd import _lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "include", "bt_si_sq.h")) as f:
+        text = f.read()
+    flags = dict(re.findall(r"#define (BT_[A-Z_]+) (0x[0-9a-f]+)u", text))
+    assert set(flags) == {"BT_DIAG_ONLY", "BT_PLAIN", "BT_GRAPH"}
+    for name, val in flags.items():
+        assert getattr(_lib, name) == int(val, 16), name
+    nums = dict(re.findall(r"#define (BT_TILE_SHAPES|BT_TUNE_SIZE_CLASSES|BT_TUNE_WORK_CLASSES) (\d+)", text))
+    for name, val in nums.items():
+        assert getattr(_lib, name) == int(val), name

@@ -25,9 +25,10 @@ SHAPES = [(1, 1, 1), (64, 32, 16), (100, 37, 53), (128, 64, 200), (5, 300, 7), (
           (512, 512, 512)]
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_gemm_fp64(torch, m, n, k, opA, opB):
+def test_gemm_fp64(torch, m, n, k, opA, opB, shape):
     from paper_2601_04904_amd.solver import diag_gemm
     rng = np.random.default_rng(m * 7 + n * 3 + k + 10 * opA + 20 * opB)
     A = crand(rng, *((k, m) if opA else (m, k)))
@@ -36,7 +37,7 @@ def test_gemm_fp64(torch, m, n, k, opA, opB):
     alpha, beta = 0.7 - 0.3j, -1.1 + 0.4j
     ref = beta * C + alpha * ((A.conj().T if opA else A) @ (B.conj().T if opB else B))
     dA, dB, dC = (torch.from_numpy(x).cuda() for x in (A, B, C))
-    out = diag_gemm(alpha, dA, opA, dB, opB, beta=beta, Cin=dC)
+    out = diag_gemm(alpha, dA, opA, dB, opB, beta=beta, Cin=dC, shape=shape)
     torch.cuda.synchronize()
     err = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
     assert err < 1e-13 * max(1, np.sqrt(k)), err
@@ -54,16 +55,17 @@ def test_gemm_in_place_and_no_c(torch):
     assert np.allclose(out0.cpu().numpy(), 2j * (A @ B), rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", [(64, 32, 16), (200, 100, 300), (384, 384, 384)])
 @pytest.mark.parametrize("opA,opB", [(0, 0), (1, 1), (0, 1)])
-def test_gemm_mixed(torch, m, n, k, opA, opB):
+def test_gemm_mixed(torch, m, n, k, opA, opB, shape):
     from paper_2601_04904_amd.solver import diag_gemm
     rng = np.random.default_rng(5)
     A = crand(rng, *((k, m) if opA else (m, k)))
     B = crand(rng, *((n, k) if opB else (k, n)))
     ref = (A.conj().T if opA else A) @ (B.conj().T if opB else B)
     dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
-    out = diag_gemm(1.0, dA, opA, dB, opB, mixed=True)
+    out = diag_gemm(1.0, dA, opA, dB, opB, mixed=True, shape=shape)
     torch.cuda.synchronize()
     err = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
     assert err < 2e-6, err     # complex64 products with FP32 accumulation
@@ -145,3 +147,34 @@ def test_inverse_pivot_choice_matters(torch):
         ref = np.linalg.inv(M)
         err = np.linalg.norm(dst.cpu().numpy()[0] - ref) / np.linalg.norm(ref)
         assert err < 1e-14 * np.sqrt(d) * 10, (d, err)
+
+
+def test_autotune_fills_table_and_solves_still_match(torch):
+    """The autotuner times every shape, stores a shape for each class it
+    reaches, and a solve compiled with the tuned table matches the oracle."""
+    from paper_2601_04904_amd import solver as S
+    import oracle
+    from paper_2601_04904_amd.synth import gen_problem
+    saved = S.tune_table()
+    try:
+        report = S.autotune()
+        assert report, "no classes timed"
+        table = S.tune_table()
+        for line in report:
+            prec, mc, tc, shape = (int(v) for v in line.split()[:4])
+            assert table[(prec * 6 + mc) * 14 + tc] == shape
+            assert all(float(v) > 0 for v in line.split()[4:])
+        A, B = gen_problem(12, 96, 40, 0.3, 1e-2, 3)
+        n, b, a = 12, 96, 40
+        dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+        XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+        sol = S.Solver(n, b, a, partitions=2)
+        sol.solve(dA, dB, XR, XL)
+        sol.sync()
+        sol.destroy()
+        from tests._util import rel_err
+        ref = oracle.solve_dense(A, B)
+        assert rel_err(XR.to_host(), ref[0]) < 1e-11
+        assert rel_err(XL.to_host(), ref[1]) < 1e-11
+    finally:
+        S.set_tune_table(saved)
