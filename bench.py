@@ -138,7 +138,9 @@ def bench_batch(args, torch, S):
         errs, fbs = [], []
         for w0 in range(0, len(specs), waves):
             sub = list(range(w0, min(len(specs), w0 + waves)))
-            precs = [router.choose(specs[i]["b"], specs[i]["a"]) if router else precision for i in sub]
+            precs = [router.choose(specs[i]["eta"], specs[i]["a"],
+                                   S.flops(specs[i]["n"], specs[i]["b"], specs[i]["a"], 1)[0])
+                     if router else precision for i in sub]
             wspecs = [dict(n=specs[i]["n"], b=specs[i]["b"], a=specs[i]["a"], precision=pr, flags=args.flags)
                       for i, pr in zip(sub, precs)]
             XR = [S.DeviceBlocks.empty(specs[i]["n"], specs[i]["b"], specs[i]["a"]) for i in sub]
@@ -159,7 +161,7 @@ def bench_batch(args, torch, S):
             if router:
                 for i, pr, fb in zip(sub, precs, f):
                     if pr == S.BT_MIXED:
-                        router.record(specs[i]["b"], specs[i]["a"], fb)
+                        router.record(specs[i]["eta"], specs[i]["a"], fb)
             bs.destroy()
             del XR, XL
         out["solves_per_s"] = round(len(specs) / t_total, 3)
@@ -175,7 +177,8 @@ def bench_batch(args, torch, S):
     from paper_2601_04904_amd.serving import PrecisionRouter
     mixed_spec = run_batched(S.BT_MIXED, args.batch_wave)
     log(f"[bench] mixed batched, every instance tried in mixed precision: {mixed_spec}")
-    mixed = run_batched(S.BT_MIXED, args.batch_wave, router=PrecisionRouter())
+    mixed = run_batched(S.BT_MIXED, args.batch_wave,
+                        router=PrecisionRouter(probe_max_flops=args.probe_max_tflop * 1e12 / 20))
     log(f"[bench] mixed batched with precision routing: {mixed}")
     fp64 = run_batched(S.BT_FP64, args.batch_wave)
     log(f"[bench] fp64 batched: {fp64}")
@@ -222,7 +225,7 @@ def bench_serve(args, torch, S):
     reqs = serving.requests_from_trace(trace)
     budget = int(args.serve_budget_gb * 1e9)
     eng = serving.ServingEngine(budget_bytes=budget, max_inflight=args.inflight, max_wave=args.max_wave,
-                                router=serving.PrecisionRouter())
+                                router=serving.PrecisionRouter(probe_max_flops=args.probe_max_tflop * 1e12))
     stats = eng.replay(reqs)
     stats["waves"] = eng.waves
     stats["errors"] = eng.errors
@@ -280,6 +283,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     ap.add_argument("--inflight", type=int, default=2)
     ap.add_argument("--max-wave", type=int, default=8)
+    ap.add_argument("--probe-max-tflop", type=float, default=2.0,
+                    help="serving: largest request (TFLOP) spent on probing the mixed path")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -15,6 +15,7 @@ times, the error estimate and whether the FP64 re-run was taken.
 """
 from __future__ import annotations
 
+import math
 import threading
 import time
 from collections import deque
@@ -79,37 +80,62 @@ class PrecisionRouter:
     The mixed path runs its bulk products in complex64 and re-runs an instance
     in FP64 when its error estimate exceeds the tolerance, so on inputs whose
     conditioning amplifies FP32 rounding past the tolerance it costs a mixed
-    run plus an FP64 run.  The router keeps, per shape class (block size and
-    whether there is an arrowhead), a running fallback rate of the mixed runs
-    it has seen; once that rate is above `threshold` (after `probe` runs),
-    further mixed requests of the class go straight to FP64, except every
-    `reprobe`-th one, which still tries the mixed path so the rate can recover.
+    run plus an FP64 run.  The conditioning of A = (E + i eta) I - H - Sigma is
+    governed mostly by the broadening eta (||A^-1|| <= 1/eta when the
+    self-energies are absorbing), so requests are classed by the decade of
+    eta and by whether there is an arrowhead.  The router keeps, per class, a
+    running fallback rate of the mixed runs it has seen; once that rate is
+    above `threshold` (after `probe` runs), further mixed requests of the class
+    go straight to FP64, except every `reprobe`-th one, which still tries the
+    mixed path so the rate can recover.
     """
 
-    def __init__(self, threshold: float = 0.5, probe: int = 2, reprobe: int = 16, decay: float = 0.8):
+    def __init__(self, threshold: float = 0.5, probe: int = 2, reprobe: int = 16, decay: float = 0.8,
+                 probe_max_flops: float = float("inf")):
         self.threshold, self.probe, self.reprobe, self.decay = threshold, probe, reprobe, decay
+        self.probe_max_flops = probe_max_flops
         self.rate = {}
         self.seen = {}
+        self.outcomes = {}
+        self.pending = {}
         self.routed = 0
         self.lock = threading.Lock()
 
     @staticmethod
-    def key(b: int, a: int):
-        return (b, a > 0)
+    def key(eta: float, a: int):
+        decade = int(math.floor(math.log10(eta))) if eta > 0 else -99
+        return (decade, a > 0)
 
-    def choose(self, b: int, a: int) -> int:
-        k = self.key(b, a)
+    def choose(self, eta: float, a: int, flops: float = 0.0) -> int:
+        """Precision to run a mixed request with.  Probes (runs whose only use
+        is to learn the class's fallback rate) are spent on requests of at most
+        probe_max_flops; a costlier request of a class without enough outcomes
+        runs in FP64."""
+        k = self.key(eta, a)
         with self.lock:
             n = self.seen.get(k, 0)
+            known = self.outcomes.get(k, 0)
+            pending = self.pending.get(k, 0)
+            cheap = flops <= self.probe_max_flops
+            if known < self.probe:
+                # no more probes in flight than still needed
+                if not cheap or known + pending >= self.probe:
+                    self.routed += 1
+                    return S.BT_FP64
+                self.pending[k] = pending + 1
+                self.seen[k] = n + 1
+                return S.BT_MIXED
             self.seen[k] = n + 1
-            if n < self.probe or self.rate.get(k, 0.0) <= self.threshold or n % self.reprobe == 0:
+            if self.rate.get(k, 0.0) <= self.threshold or (cheap and n % self.reprobe == 0):
                 return S.BT_MIXED
             self.routed += 1
             return S.BT_FP64
 
-    def record(self, b: int, a: int, fell_back: bool):
-        k = self.key(b, a)
+    def record(self, eta: float, a: int, fell_back: bool):
+        k = self.key(eta, a)
         with self.lock:
+            self.outcomes[k] = self.outcomes.get(k, 0) + 1
+            self.pending[k] = max(0, self.pending.get(k, 0) - 1)
             r = self.rate.get(k, float(fell_back))
             self.rate[k] = self.decay * r + (1.0 - self.decay) * float(fell_back)
 
@@ -135,6 +161,9 @@ class ServingEngine:
         self.max_used = 0
         self.router = router
         self.oom_retries = 0
+        self.release_above = 8 << 30      # cached-but-unused torch memory released before a wave
+        self.size_ratio = 8.0             # largest work ratio between requests of one wave
+        self.threads = []
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -154,12 +183,19 @@ class ServingEngine:
             self.pending.append(req)
 
     def _take_wave(self):
-        """FIFO requests that fit the memory budget (head-of-line order kept)."""
+        """FIFO requests that fit the memory budget (head-of-line order kept).
+        A wave finishes with its slowest request, so it stops at the first
+        request whose work differs from the wave's first one by more than
+        `size_ratio` either way; that request heads the next wave."""
         wave = []
         while self.pending and len(wave) < self.max_wave:
             r = self.pending[0]
             if self.used + r.footprint > self.budget:
                 break
+            if wave:
+                ratio = r.flops() / max(wave[0].flops(), 1.0)
+                if ratio > self.size_ratio or ratio < 1.0 / self.size_ratio:
+                    break
             self.pending.popleft()
             self.used += r.footprint
             self.max_used = max(self.max_used, self.used)
@@ -181,7 +217,7 @@ class ServingEngine:
                 if self.router is not None:
                     for r in wave:
                         if r.precision == "mixed":
-                            r.run_precision = self.router.choose(r.b, r.a)
+                            r.run_precision = self.router.choose(r.eta, r.a, r.flops())
                 bs = self._batch_solver([r.spec() for r in wave], stream)
                 err, fb = bs.solve([x[0] for x in inputs], [x[1] for x in inputs], XR, XL)
                 errs = [[e] for e in err]
@@ -200,7 +236,7 @@ class ServingEngine:
                 if self.router is not None:
                     for i, r in enumerate(wave):
                         if r.spec()["precision"] == S.BT_MIXED:
-                            self.router.record(r.b, r.a, bool(fbs[i][0]))
+                            self.router.record(r.eta, r.a, bool(fbs[i][0]))
                 for i, r in enumerate(wave):
                     r.t_done = t_done
                     r.err = errs[i]
@@ -223,7 +259,8 @@ class ServingEngine:
         so blocks that torch has cached (the input generator's temporaries) are
         released first; an allocation failure is retried once after that."""
         torch = self.torch
-        torch.cuda.empty_cache()
+        if torch.cuda.memory_reserved() - torch.cuda.memory_allocated() > self.release_above:
+            torch.cuda.empty_cache()
         try:
             return S.BatchSolver(specs, stream=stream)
         except S.BTError as ex:
@@ -244,7 +281,9 @@ class ServingEngine:
                 return False
             self.busy += 1
             self.waves += 1
-        threading.Thread(target=self._run_wave, args=(wave,), daemon=True).start()
+        th = threading.Thread(target=self._run_wave, args=(wave,))
+        self.threads.append(th)
+        th.start()
         return True
 
     def replay(self, requests, poll: float = 0.0005):
@@ -266,7 +305,11 @@ class ServingEngine:
                 if len(self.done) == total:
                     break
                 self.cv.wait(timeout=poll)
-        return summarize(self.done, self.now())
+        wall = self.now()
+        for th in self.threads:          # no worker outlives the replay
+            th.join()
+        self.threads = []
+        return summarize(self.done, wall)
 
 
 def summarize(done, wall):
