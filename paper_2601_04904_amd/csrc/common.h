@@ -54,8 +54,8 @@ __device__ inline int xcd_remap(int b, int g) {
 struct InvJob {
     const double2* src;
     double2* dst;
-    double2* W;       // d x d working copy
-    double2* Mm;      // 2 x (d x kInvNB): panel transform minus pivot columns, by panel parity
+    double2* W;       // d x d working copy, column-major
+    double2* Mm;      // 2 x (d x kInvNB) column-major: panel transform minus pivot columns, by panel parity
     int32_t* perm;    // d pivot rows (perm[j] = pivot row of column j)
     int32_t* used;    // d flags
     int32_t d;

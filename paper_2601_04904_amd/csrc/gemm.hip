@@ -88,64 +88,99 @@ typedef const __attribute__((address_space(1))) double2* gptr_t;
 typedef const double2* gptr_t;
 #endif
 
-// Raw operands of one stage in flight: values, in-range flags and the term's
-// op / alpha needed to finish them.
+// Addressing of one thread's loads for one product term, fixed over all k
+// stages of the term: the pointer to its operand row (A) or column (B) at
+// k = 0, whether that row or column lies inside the matrix, and the element
+// stride between consecutive k.  The term's flags, k and alpha come from the
+// op list in global memory at a uniform address, so they are wave-uniform and
+// the choices on them are scalar.
+template <int BM, int BN>
+struct TermAddr {
+    static constexpr int NA = BM * kBK / kThreads;
+    static constexpr int NB = BN * kBK / kThreads;
+    gptr_t pa[NA];
+    gptr_t pb[NB];
+    unsigned rowok;       // bit q: A row of load q in range; bit NA + q: B column of load q
+    int ksa, ksb;
+    int km1;
+    bool ah, bh;
+    int akind;            // alpha: 0 general, 1 exactly +1, 2 exactly -1
+    double2 alpha;
+};
+
+// Coordinates of load e (= tid + kThreads q) inside the stage tile: A (i, p)
+// and B (j, p), chosen so that consecutive threads read consecutive memory.
+template <int BM> __device__ inline int a_i(bool ah, int e) { return ah ? (e % BM) : (e / kBK); }
+template <int BM> __device__ inline int a_p(bool ah, int e) { return ah ? (e / BM) : (e % kBK); }
+template <int BN> __device__ inline int b_j(bool bh, int e) { return bh ? (e / kBK) : (e % BN); }
+template <int BN> __device__ inline int b_p(bool bh, int e) { return bh ? (e % kBK) : (e / BN); }
+
+template <int BM, int BN>
+__device__ inline void term_setup(const GemmTerm& T, int m, int n, int i0, int j0, int tid,
+                                  TermAddr<BM, BN>& ta) {
+    ta.ah = T.flags & kTermAH;
+    ta.bh = T.flags & kTermBH;
+    ta.km1 = T.k - 1;
+    ta.alpha = T.alpha;
+    ta.akind = T.alpha.y != 0.0 ? 0 : T.alpha.x == 1.0 ? 1 : T.alpha.x == -1.0 ? 2 : 0;
+    ta.ksa = ta.ah ? T.lda : 1;
+    ta.ksb = ta.bh ? 1 : T.ldb;
+    ta.rowok = 0;
+    const gptr_t Ap = (gptr_t)T.A;
+    const gptr_t Bp = (gptr_t)T.B;
+#pragma unroll
+    for (int q = 0; q < ta.NA; ++q) {
+        const int gi = i0 + a_i<BM>(ta.ah, tid + kThreads * q);
+        const int gic = min(gi, m - 1);
+        ta.pa[q] = ta.ah ? Ap + gic : Ap + (size_t)gic * T.lda;
+        ta.rowok |= (gi < m ? 1u : 0u) << q;
+    }
+#pragma unroll
+    for (int q = 0; q < ta.NB; ++q) {
+        const int gj = j0 + b_j<BN>(ta.bh, tid + kThreads * q);
+        const int gjc = min(gj, n - 1);
+        ta.pb[q] = ta.bh ? Bp + (size_t)gjc * T.ldb : Bp + gjc;
+        ta.rowok |= (gj < n ? 1u : 0u) << (ta.NA + q);
+    }
+}
+
+// Raw operands of one stage in flight and their in-range flags.
 template <int BM, int BN>
 struct Stage {
     double2 ra[BM * kBK / kThreads];
     double2 rb[BN * kBK / kThreads];
-    bool oka[BM * kBK / kThreads];
-    bool okb[BN * kBK / kThreads];
-    bool ah, bh;
-    double2 alpha;
+    unsigned ok;
 };
 
-// Issue the global loads of one stage of term T at k offset k0.  Loads are
-// unconditional (indices clamped into the matrix; out-of-range values are
-// replaced by zero in finish_stage) so that they are all in flight together
-// and overlap the MFMAs of the current stage.
+// Issue the global loads of one stage at k offset k0.  Loads are
+// unconditional (k clamped into the term; out-of-range values are replaced by
+// zero in finish_stage) so that they are all in flight together and overlap
+// the MFMAs of the current stage.
 template <int BM, int BN>
-__device__ inline void issue_stage(const GemmTerm& T, int m, int n, int i0, int j0, int k0,
-                                   int tid, Stage<BM, BN>& st) {
+__device__ inline void issue_stage(const TermAddr<BM, BN>& ta, int k0, int tid, Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
     constexpr int NB = BN * kBK / kThreads;
-    const bool ah = T.flags & kTermAH;
-    const bool bh = T.flags & kTermBH;
-    st.ah = ah;
-    st.bh = bh;
-    st.alpha = T.alpha;
-    const int km1 = T.k - 1;
-    const gptr_t Ap = (gptr_t)T.A;
-    const gptr_t Bp = (gptr_t)T.B;
+    unsigned ok = 0;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-        const int e = tid + kThreads * q;
-        const int i = ah ? (e % BM) : (e / kBK);
-        const int p = ah ? (e / BM) : (e % kBK);
-        const int gi = i0 + i, gp = k0 + p;
-        st.oka[q] = gi < m && gp <= km1;
-        const int gic = min(gi, m - 1), gpc = min(gp, km1);
-        const size_t idx = ah ? (size_t)gpc * T.lda + gic : (size_t)gic * T.lda + gpc;
-        st.ra[q] = Ap[idx];
+        const int gp = k0 + a_p<BM>(ta.ah, tid + kThreads * q);
+        ok |= (gp <= ta.km1 ? 1u : 0u) << q;
+        st.ra[q] = ta.pa[q][(size_t)min(gp, ta.km1) * ta.ksa];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int e = tid + kThreads * q;
-        const int j = bh ? (e / kBK) : (e % BN);
-        const int p = bh ? (e % kBK) : (e / BN);
-        const int gj = j0 + j, gp = k0 + p;
-        st.okb[q] = gj < n && gp <= km1;
-        const int gjc = min(gj, n - 1), gpc = min(gp, km1);
-        const size_t idx = bh ? (size_t)gjc * T.ldb + gpc : (size_t)gpc * T.ldb + gjc;
-        st.rb[q] = Bp[idx];
+        const int gp = k0 + b_p<BN>(ta.bh, tid + kThreads * q);
+        ok |= (gp <= ta.km1 ? 1u : 0u) << (NA + q);
+        st.rb[q] = ta.pb[q][(size_t)min(gp, ta.km1) * ta.ksb];
     }
+    st.ok = ok & ta.rowok;
 }
 
 // Conjugate, scale by alpha and zero the out-of-range values.  The empty asm
 // consumes every loaded value, so the compiler cannot turn the loads back
 // into conditional ones.
 template <int BM, int BN>
-__device__ inline void finish_stage(Stage<BM, BN>& st) {
+__device__ inline void finish_stage(const TermAddr<BM, BN>& ta, Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
     constexpr int NB = BN * kBK / kThreads;
 #pragma unroll
@@ -155,20 +190,21 @@ __device__ inline void finish_stage(Stage<BM, BN>& st) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         double2 v = st.ra[q];
-        v.y = st.ah ? -v.y : v.y;
-        st.ra[q] = st.oka[q] ? v : make_double2(0.0, 0.0);
+        if (ta.ah) v.y = -v.y;
+        st.ra[q] = (st.ok >> q) & 1 ? v : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         double2 v = st.rb[q];
-        v.y = st.bh ? -v.y : v.y;
-        v = cmul(st.alpha, v);
-        st.rb[q] = st.okb[q] ? v : make_double2(0.0, 0.0);
+        if (ta.bh) v.y = -v.y;
+        if (ta.akind == 2) { v.x = -v.x; v.y = -v.y; }
+        else if (ta.akind == 0) v = cmul(ta.alpha, v);
+        st.rb[q] = (st.ok >> (NA + q)) & 1 ? v : make_double2(0.0, 0.0);
     }
 }
 
 template <bool MIXED, int BM, int BN>
-__device__ inline void store_stage(int tid, const Stage<BM, BN>& st,
+__device__ inline void store_stage(const TermAddr<BM, BN>& ta, int tid, const Stage<BM, BN>& st,
                                    typename Prec<MIXED>::C (*As)[BM + 1],
                                    typename Prec<MIXED>::C (*Bs)[BN + 1]) {
     constexpr int NA = BM * kBK / kThreads;
@@ -176,16 +212,12 @@ __device__ inline void store_stage(int tid, const Stage<BM, BN>& st,
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         const int e = tid + kThreads * q;
-        const int i = st.ah ? (e % BM) : (e / kBK);
-        const int p = st.ah ? (e / BM) : (e % kBK);
-        As[p][i] = Prec<MIXED>::cvt(st.ra[q]);
+        As[a_p<BM>(ta.ah, e)][a_i<BM>(ta.ah, e)] = Prec<MIXED>::cvt(st.ra[q]);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int e = tid + kThreads * q;
-        const int j = st.bh ? (e / kBK) : (e % BN);
-        const int p = st.bh ? (e % kBK) : (e / BN);
-        Bs[p][j] = Prec<MIXED>::cvt(st.rb[q]);
+        Bs[b_p<BN>(ta.bh, e)][b_j<BN>(ta.bh, e)] = Prec<MIXED>::cvt(st.rb[q]);
     }
 }
 
@@ -202,7 +234,6 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     constexpr int NI = BN / 16;
     __shared__ CT As[2][kBK][BM + 1];
     __shared__ CT Bs[2][kBK][BN + 1];
-    __shared__ GemmTerm terms[kMaxTerms];
 
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const GemmOp* op = ops + find_op(ops, nops, bid);
@@ -211,8 +242,7 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     const int tm = local / op->tiles_n, tn = local - tm * op->tiles_n;
     const int i0 = tm * BM, j0 = tn * BN;
     const int tid = threadIdx.x;
-    if (tid < nterms) terms[tid] = op->t[tid];
-    __syncthreads();
+    const GemmTerm* terms = op->t;     // uniform: read with scalar loads
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -238,18 +268,23 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     int t = 0, k0 = 0;
     while (t < nterms && terms[t].k <= 0) ++t;
     Stage<BM, BN> st;
+    TermAddr<BM, BN> ta;
     int buf = 0;
     if (t < nterms) {
-        issue_stage<BM, BN>(terms[t], m, n, i0, j0, k0, tid, st);
-        finish_stage<BM, BN>(st);
-        store_stage<MIXED, BM, BN>(tid, st, As[0], Bs[0]);
+        term_setup<BM, BN>(terms[t], m, n, i0, j0, tid, ta);
+        issue_stage<BM, BN>(ta, k0, tid, st);
+        finish_stage<BM, BN>(ta, st);
+        store_stage<MIXED, BM, BN>(ta, tid, st, As[0], Bs[0]);
     }
     __syncthreads();
     while (t < nterms) {
         int tn2 = t, kn = k0 + kBK;
         while (tn2 < nterms && kn >= terms[tn2].k) { ++tn2; kn = 0; }
         const bool has_next = tn2 < nterms;
-        if (has_next) issue_stage<BM, BN>(terms[tn2], m, n, i0, j0, kn, tid, st);
+        if (has_next) {
+            if (tn2 != t) term_setup<BM, BN>(terms[tn2], m, n, i0, j0, tid, ta);
+            issue_stage<BM, BN>(ta, kn, tid, st);
+        }
 
 #pragma unroll
         for (int kk = 0; kk < kBK / 2; ++kk) {
@@ -275,8 +310,8 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
                     acc[g][ni] = Prec<MIXED>::mfma(av[g], bv[ni], acc[g][ni]);
         }
         if (has_next) {
-            finish_stage<BM, BN>(st);
-            store_stage<MIXED, BM, BN>(tid, st, As[buf ^ 1], Bs[buf ^ 1]);
+            finish_stage<BM, BN>(ta, st);
+            store_stage<MIXED, BM, BN>(ta, tid, st, As[buf ^ 1], Bs[buf ^ 1]);
         }
         __syncthreads();
         buf ^= 1;

@@ -9,6 +9,11 @@
 // (M A = Q, Q the permutation with Q e_j = e_{p_j}), so at the end
 //     A^-1[j][c] = W[p_j][pinv(c)].
 //
+// Layout: the working matrix W (d x d) and the panel transforms Mm (d x NB)
+// are stored column-major, element (r, c) at c * d + r.  Every kernel below
+// gives each lane its own rows, so a load or store of one column by a wave
+// covers 64 consecutive rows (1 KB) instead of 64 scattered pieces.
+//
 // Blocking: a panel of kInvNB columns is eliminated by one workgroup that
 // holds the panel rows in registers (one barrier per column: the best
 // candidate of every wave publishes its row and the reciprocal of its pivot
@@ -95,14 +100,26 @@ __device__ inline int key_row(double key) {
     return 2047 - (int)(__double_as_longlong(key) & 2047ll);
 }
 
+// W = src transposed into the column-major working layout, through 16 x 16
+// LDS tiles so that both the row-major reads and the column-major writes are
+// contiguous across threads.  256 threads per workgroup.
 __global__ void inv_init(const InvJob* __restrict__ jobs) {
+    __shared__ double2 tile[16][17];
     const InvJob J = jobs[blockIdx.y];
-    const size_t total = (size_t)J.d * J.d;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride)
-        J.W[e] = J.src[e];
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)J.d; e += stride)
-        J.used[e] = 0;
+    const int d = J.d;
+    const int nt = (d + 15) / 16;
+    const int tid = threadIdx.x;
+    const int a = tid >> 4, b = tid & 15;
+    for (int t = blockIdx.x; t < nt * nt; t += gridDim.x) {
+        const int ti = t / nt, tj = t - ti * nt;
+        const int r = ti * 16 + a, c = tj * 16 + b;
+        if (r < d && c < d) tile[a][b] = J.src[(size_t)r * d + c];
+        __syncthreads();
+        const int c2 = tj * 16 + a, r2 = ti * 16 + b;
+        if (r2 < d && c2 < d) J.W[(size_t)c2 * d + r2] = tile[b][a];
+        __syncthreads();
+    }
+    for (int e = blockIdx.x * blockDim.x + tid; e < d; e += gridDim.x * blockDim.x) J.used[e] = 0;
 }
 
 // One launch per panel p.  Per matrix, workgroup 0 (the panel workgroup)
@@ -129,7 +146,7 @@ __device__ void step_update(const InvJob& J, int p, int u, int tid) {
     if (tid < NB * UC) {
         const int s = tid / UC, j = tid % UC;
         const int sr = min(s, nc - 1), cc = min(c0 + j, d - 1);
-        const double2 v = J.W[(size_t)J.perm[q0 + sr] * d + cc];
+        const double2 v = J.W[(size_t)cc * d + J.perm[q0 + sr]];
         G[s][j] = (s < nc && c0 + j < d) ? v : make_double2(0.0, 0.0);
     }
     __syncthreads();
@@ -139,15 +156,15 @@ __device__ void step_update(const InvJob& J, int p, int u, int tid) {
         const int r = tid + q * T;
         if (r >= d) continue;
         double2 acc[UC];
-        const double2* wrow = J.W + (size_t)r * d + c0;
-        const double2* mrow = Mm + (size_t)r * NB;
+        const double2* wcol = J.W + (size_t)c0 * d + r;
+        const double2* mcol = Mm + r;
 #pragma unroll
-        for (int j = 0; j < UC; ++j) acc[j] = wrow[min(j, ncols - 1)];
+        for (int j = 0; j < UC; ++j) acc[j] = wcol[(size_t)min(j, ncols - 1) * d];
 #pragma unroll 2
         for (int s = 0; s < NB; s += 4) {
             double2 m[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) m[i] = mrow[s + i];
+            for (int i = 0; i < 4; ++i) m[i] = mcol[(size_t)(s + i) * d];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -155,10 +172,10 @@ __device__ void step_update(const InvJob& J, int p, int u, int tid) {
                     cfma(acc[j], m[i], G[s + i][j]);
                 }
         }
-        double2* wout = J.W + (size_t)r * d + c0;
+        double2* wout = J.W + (size_t)c0 * d + r;
 #pragma unroll
         for (int j = 0; j < UC; ++j)
-            if (j < ncols) wout[j] = acc[j];
+            if (j < ncols) wout[(size_t)j * d] = acc[j];
     }
 }
 
@@ -187,10 +204,10 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = min(tid + q * T, d - 1);
-        const double2* row = J.W + (size_t)r * d + j0;
+        const double2* col = J.W + (size_t)j0 * d + r;
         used[q] = J.used[r];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) P[q][c] = row[min(c, nc - 1)];
+        for (int c = 0; c < NB; ++c) P[q][c] = col[(size_t)min(c, nc - 1) * d];
     }
     if (p > 0) {
         const int q0 = (p - 1) * NB;
@@ -200,9 +217,9 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
         double2 m[R][MG];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const double2* mrow = Mm + (size_t)min(tid + q * T, d - 1) * NB;
+            const double2* mcol = Mm + min(tid + q * T, d - 1);
 #pragma unroll
-            for (int i = 0; i < MG; ++i) m[q][i] = mrow[i];
+            for (int i = 0; i < MG; ++i) m[q][i] = mcol[(size_t)i * d];
         }
         if (tid < NB) prev[tid] = tid < pnc ? J.perm[q0 + tid] : -1;
         if (tid < NB && tid >= pnc) {
@@ -231,9 +248,9 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
             if (s0 > 0) {
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    const double2* mrow = Mm + (size_t)min(tid + q * T, d - 1) * NB;
+                    const double2* mcol = Mm + min(tid + q * T, d - 1);
 #pragma unroll
-                    for (int i = 0; i < MG; ++i) m[q][i] = mrow[s0 + i];
+                    for (int i = 0; i < MG; ++i) m[q][i] = mcol[(size_t)(s0 + i) * d];
                 }
             }
 #pragma unroll
@@ -365,17 +382,17 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     for (int q = 0; q < R; ++q) {
         const int r = tid + q * T;
         if (r < d) {
-            double2* row = J.W + (size_t)r * d + j0;
-            double2* mrow = Mm + (size_t)r * NB;
+            double2* col = J.W + (size_t)j0 * d + r;
+            double2* mcol = Mm + r;
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 if (c < nc) {
                     double2 v = cmul_i(sc[q], P[q][c]);
-                    row[c] = v;
+                    col[(size_t)c * d] = v;
                     if (piv[c] == r) v.x -= 1.0;
-                    mrow[c] = v;
+                    mcol[(size_t)c * d] = v;
                 } else {
-                    mrow[c] = make_double2(0.0, 0.0);
+                    mcol[(size_t)c * d] = make_double2(0.0, 0.0);
                 }
             }
             J.used[r] = used[q];
@@ -405,9 +422,9 @@ __global__ void inv_finish(const InvJob* __restrict__ jobs) {
     for (int e = threadIdx.x; e < d; e += blockDim.x) pinv[perm[e]] = e;
     __syncthreads();
     for (int j = blockIdx.x; j < d; j += gridDim.x) {
-        const double2* src = J.W + (size_t)perm[j] * d;
+        const double2* src = J.W + perm[j];           // row perm[j] of the column-major W
         double2* dst = J.dst + (size_t)j * d;
-        for (int c = threadIdx.x; c < d; c += blockDim.x) dst[c] = src[pinv[c]];
+        for (int c = threadIdx.x; c < d; c += blockDim.x) dst[c] = src[(size_t)pinv[c] * d];
     }
 }
 
