@@ -264,6 +264,31 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
 #pragma unroll
         for (int b = 0; b < NI; ++b)
             acc[a][b] = AccT{};
+    if constexpr (!MIXED) {
+        // FP64: the accumulators start at beta C (C read before any of D is
+        // written, so C may be D), and the epilogue only stores.
+        if (op->C) {
+            const gptr_t Cp = (gptr_t)op->C;
+            const int ldc = op->ldc;
+            const double2 beta = op->beta;
+            double2 cv[RG][NI];
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int ni = 0; ni < NI; ++ni) {
+                    const int row = min(i0 + wm * (BM / 2) + g * 4 + (lane >> 4), m - 1);
+                    const int col = min(j0 + ((wn * BN + ni * 16 + r16) >> 1), n - 1);
+                    cv[g][ni] = Cp[(size_t)row * ldc + col];
+                }
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int ni = 0; ni < NI; ++ni) {
+                    const double2 c = cv[g][ni];
+                    acc[g][ni] = d ? (beta.x * c.y + beta.y * c.x) : (beta.x * c.x - beta.y * c.y);
+                }
+        }
+    }
 
     int t = 0, k0 = 0;
     while (t < nterms && terms[t].k <= 0) ++t;
@@ -327,7 +352,7 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     const double2* C = op->C;
     const int ldd = op->ldd, ldc = op->ldc;
     const double2 beta = op->beta;
-    if (C) {
+    if (MIXED && C) {
         // all C loads first (clamped, unconditional), then the stores
         double2 cv[RG][NI][NR];
         const gptr_t Cp = (gptr_t)C;
