@@ -19,6 +19,7 @@
 // FP32 while staging into LDS, v_mfma_f32_16x16x4f32 with FP32 accumulation,
 // the result added to the FP64 output in FP64.
 #include "common.h"
+#include <type_traits>
 
 namespace btsq {
 
@@ -290,27 +291,50 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
         }
     }
 
-    int t = 0, k0 = 0;
-    while (t < nterms && terms[t].k <= 0) ++t;
-    Stage<BM, BN> st;
+    // Stages are (term, k offset) pairs in order; next() steps to the
+    // following one, skipping empty terms.  Two register sets hold the raw
+    // operands of the next two stages, so within a term the global loads of
+    // a stage are issued two stages ahead of its MFMAs; at a term boundary
+    // the new term's first stage is issued one stage ahead (the addressing
+    // `ta` describes one term at a time).
+    auto next = [&](int& t, int& k0) {
+        k0 += kBK;
+        while (t < nterms && k0 >= terms[t].k) { ++t; k0 = 0; }
+    };
+    int t1 = 0, k1 = 0;
+    while (t1 < nterms && terms[t1].k <= 0) ++t1;
+    Stage<BM, BN> st[2];
     TermAddr<BM, BN> ta;
-    int buf = 0;
-    if (t < nterms) {
-        term_setup<BM, BN>(terms[t], m, n, i0, j0, tid, ta);
-        issue_stage<BM, BN>(ta, k0, tid, st);
-        finish_stage<BM, BN>(ta, st);
-        store_stage<MIXED, BM, BN>(ta, tid, st, As[0], Bs[0]);
+    int ta_term = -1;
+    bool cur = false, fly = false;
+    if (t1 < nterms) {
+        term_setup<BM, BN>(terms[t1], m, n, i0, j0, tid, ta);
+        ta_term = t1;
+        issue_stage<BM, BN>(ta, k1, tid, st[0]);
+        finish_stage<BM, BN>(ta, st[0]);
+        store_stage<MIXED, BM, BN>(ta, tid, st[0], As[0], Bs[0]);
+        cur = true;
+        next(t1, k1);
+        if (t1 < nterms) {
+            if (t1 != ta_term) { term_setup<BM, BN>(terms[t1], m, n, i0, j0, tid, ta); ta_term = t1; }
+            issue_stage<BM, BN>(ta, k1, tid, st[1]);
+            fly = true;
+        }
     }
     __syncthreads();
-    while (t < nterms) {
-        int tn2 = t, kn = k0 + kBK;
-        while (tn2 < nterms && kn >= terms[tn2].k) { ++tn2; kn = 0; }
-        const bool has_next = tn2 < nterms;
-        if (has_next) {
-            if (tn2 != t) term_setup<BM, BN>(terms[tn2], m, n, i0, j0, tid, ta);
-            issue_stage<BM, BN>(ta, kn, tid, st);
-        }
+    int buf = 0;
 
+    // one stage: X = register set in flight (the next stage), Y = free set
+    auto step = [&](auto xs) {
+        constexpr int X = decltype(xs)::value, Y = 1 - X;
+        int t2 = t1, k2 = k1;
+        bool fly2 = false;
+        if (fly) {
+            next(t2, k2);
+            fly2 = t2 < nterms;
+        }
+        const bool early = fly2 && t2 == ta_term;
+        if (early) issue_stage<BM, BN>(ta, k2, tid, st[Y]);
 #pragma unroll
         for (int kk = 0; kk < kBK / 2; ++kk) {
             const int p = 2 * kk + pOff;
@@ -334,14 +358,26 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
                 for (int ni = 0; ni < NI; ++ni)
                     acc[g][ni] = Prec<MIXED>::mfma(av[g], bv[ni], acc[g][ni]);
         }
-        if (has_next) {
-            finish_stage<BM, BN>(ta, st);
-            store_stage<MIXED, BM, BN>(ta, tid, st, As[buf ^ 1], Bs[buf ^ 1]);
+        if (fly) {
+            finish_stage<BM, BN>(ta, st[X]);
+            store_stage<MIXED, BM, BN>(ta, tid, st[X], As[buf ^ 1], Bs[buf ^ 1]);
+        }
+        if (fly2 && !early) {
+            term_setup<BM, BN>(terms[t2], m, n, i0, j0, tid, ta);
+            ta_term = t2;
+            issue_stage<BM, BN>(ta, k2, tid, st[Y]);
         }
         __syncthreads();
+        cur = fly;
+        fly = fly2;
+        t1 = t2;
+        k1 = k2;
         buf ^= 1;
-        t = tn2;
-        k0 = kn;
+    };
+    while (cur) {
+        step(std::integral_constant<int, 1>{});
+        if (!cur) break;
+        step(std::integral_constant<int, 0>{});
     }
 
     // Epilogue: lane holds real column lane%16 (component lane%2 of complex
