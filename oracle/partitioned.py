@@ -17,6 +17,11 @@ solved with the sequential BTA RGF, after which every partition runs its
 backward sweep (selected inversion and quadratic solve) in reverse
 elimination order.  The per-block step is the Schur-complement step of
 rgf.forward_step / rgf.backward_step.
+
+With reduced_split=True a reduced system without tip and of at least four
+blocks is itself solved by this partitioned elimination with two partitions
+(its first half top-down, its second half bottom-up, then its two middle
+blocks): the same selected blocks in exact arithmetic, in another order.
 """
 from __future__ import annotations
 
@@ -130,7 +135,7 @@ def reduced_system(A, B, bounds):
     return Ar, Br, reduced
 
 
-def prgf(A, B, bounds):
+def prgf(A, B, bounds, reduced_split=False):
     """Partitioned SI (+ SQ when B is given).  Returns (X^R, X^<) as Sel."""
     n, b = A.diag.shape[0], A.diag.shape[1]
     a = A.tip.shape[0]
@@ -145,8 +150,11 @@ def prgf(A, B, bounds):
         return from_dicts(XR, n, b, a), (from_dicts(XL, n, b, a) if quad else None)
     Ar = _Reduced(At, reduced, a)
     Br = _Reduced(Bt, reduced, a) if quad else None
-    YR, YL = rgf_bta(Ar, Br)
     m = len(reduced)
+    if reduced_split and a == 0 and m >= 4:
+        YR, YL = prgf(Ar, Br, [0, m // 2, m])
+    else:
+        YR, YL = rgf_bta(Ar, Br)
     for Y, X in ((YR, XR), (YL, XL)) if quad else ((YR, XR),):
         for j, r in enumerate(reduced):
             X[(r, r)] = Y.diag[j]

@@ -586,14 +586,34 @@ struct Builder {
                 }
             }
             const auto& R = ps.reduced;
-            for (size_t j = 0; j < R.size(); ++j) {
-                std::vector<int> N;
-                if (j + 1 < R.size()) N.push_back(R[j + 1]);
-                if (arrow) N.push_back(t);
-                red.push_back(forward(R[j], N, 0, true));
+            const size_t m = R.size();
+            if (!arrow && m >= 4) {
+                // The reduced system is itself a BT matrix; it is split like a
+                // two-partition solve: its first half eliminated top-down, its
+                // second half bottom-up (concurrently: the halves touch
+                // disjoint blocks and create no fill), then the two middle
+                // blocks in sequence.  Its sequential chain shrinks from m to
+                // m/2 + 1 inverses.  (With an arrowhead both halves would update
+                // the tip, so that case keeps the sequential sweep.)
+                const size_t h = m / 2;
+                std::vector<StepRec> top, bot, mid;
+                for (size_t j = 0; j + 1 < h; ++j) top.push_back(forward(R[j], {R[j + 1]}, 0, true));
+                for (size_t j = m - 1; j > h; --j) bot.push_back(forward(R[j], {R[j - 1]}, 0, true));
+                mid.push_back(forward(R[h - 1], {R[h]}, 0, true));
+                mid.push_back(forward(R[h], {}, 0, true));
+                for (auto it = mid.rbegin(); it != mid.rend(); ++it) backward(*it);
+                for (auto it = top.rbegin(); it != top.rend(); ++it) backward(*it);
+                for (auto it = bot.rbegin(); it != bot.rend(); ++it) backward(*it);
+            } else {
+                for (size_t j = 0; j < m; ++j) {
+                    std::vector<int> N;
+                    if (j + 1 < m) N.push_back(R[j + 1]);
+                    if (arrow) N.push_back(t);
+                    red.push_back(forward(R[j], N, 0, true));
+                }
+                if (arrow) red.push_back(forward(t, {}, 0, true));
+                for (auto it = red.rbegin(); it != red.rend(); ++it) backward(*it);
             }
-            if (arrow) red.push_back(forward(t, {}, 0, true));
-            for (auto it = red.rbegin(); it != red.rend(); ++it) backward(*it);
         }
         for (size_t p = 0; p < recs.size(); ++p)
             for (auto it = recs[p].rbegin(); it != recs[p].rend(); ++it) backward(*it);

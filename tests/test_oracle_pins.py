@@ -26,6 +26,8 @@ SOLVERS = {
     "rgf_bta": lambda A, B: oracle.rgf_bta(A, B),
     "prgf2": lambda A, B: oracle.prgf(A, B, even_bounds(A.diag.shape[0], 2)),
     "prgf3": lambda A, B: oracle.prgf(A, B, even_bounds(A.diag.shape[0], 3)),
+    # reduced system (4 blocks without tip) solved by the two-partition split
+    "prgf3_split": lambda A, B: oracle.prgf(A, B, even_bounds(A.diag.shape[0], 3), reduced_split=True),
 }
 
 
@@ -266,6 +268,8 @@ def test_brute_force_tiny(n, b, a):
     for P in range(1, 5):
         for bounds in _all_bounds(n, P):
             cands.append(oracle.prgf(A, B, bounds))
+            if a == 0 and P >= 3:
+                cands.append(oracle.prgf(A, B, bounds, reduced_split=True))
     # rounding differs between elimination orders; mistakes give O(1) errors
     for XR, XL in cands:
         assert rel_err(XR, XR0) < 1e-11
@@ -314,3 +318,17 @@ def test_reduced_system_is_dense_schur_complement(n, b, a, bounds):
         t = slice(m * b, m * b + a)
         assert np.allclose(got_A[t, :], S_A[t, :], atol=1e-12 * np.abs(S_A).max())
         assert np.allclose(got_B[:, t], S_B[:, t], atol=1e-12 * np.abs(S_B).max())
+
+
+def test_reduced_split_runs_another_order():
+    """The split solve of the reduced system takes a different elimination
+    order (so its rounding differs from the sequential one) and reaches the
+    same selected blocks."""
+    A, B = gen_problem(12, 5, 0, E=0.2, eta=1e-2, seed=77)
+    bounds = [0, 3, 6, 9, 12]                     # reduced system of 6 blocks
+    XR1, XL1 = oracle.prgf(A, B, bounds)
+    XR2, XL2 = oracle.prgf(A, B, bounds, reduced_split=True)
+    assert not np.array_equal(np.asarray(XR1.diag), np.asarray(XR2.diag))
+    XR0, XL0 = oracle.solve_dense(A, B)
+    assert rel_err(XR2, XR0) < 1e-11 and rel_err(XL2, XL0) < 1e-10
+    assert rel_err(XR1, XR0) < 1e-11 and rel_err(XL1, XL0) < 1e-10
