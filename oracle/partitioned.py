@@ -18,10 +18,11 @@ backward sweep (selected inversion and quadratic solve) in reverse
 elimination order.  The per-block step is the Schur-complement step of
 rgf.forward_step / rgf.backward_step.
 
-With reduced_split=True a reduced system without tip and of at least four
-blocks is itself solved by this partitioned elimination with two partitions
-(its first half top-down, its second half bottom-up, then its two middle
-blocks): the same selected blocks in exact arithmetic, in another order.
+With reduced_split=True a reduced system of at least four blocks is itself
+solved by this partitioned elimination with two partitions (its first half
+top-down, its second half bottom-up, each with its own tip contribution,
+then its two middle blocks and the tip): the same selected blocks in exact
+arithmetic, in another order.
 """
 from __future__ import annotations
 
@@ -151,7 +152,7 @@ def prgf(A, B, bounds, reduced_split=False):
     Ar = _Reduced(At, reduced, a)
     Br = _Reduced(Bt, reduced, a) if quad else None
     m = len(reduced)
-    if reduced_split and a == 0 and m >= 4:
+    if reduced_split and m >= 4:
         YR, YL = prgf(Ar, Br, [0, m // 2, m])
     else:
         YR, YL = rgf_bta(Ar, Br)

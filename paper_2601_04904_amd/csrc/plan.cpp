@@ -558,6 +558,21 @@ struct Builder {
         ops.push_back(op);
     }
 
+    // tip (t,t) = tip + the accumulators of the given tags, for A and B
+    void sum_tip(const std::vector<int>& tags) {
+        const int t = D.n;
+        for (int isB = 0; isB < 2; ++isB) {
+            std::vector<std::pair<double2, MatRef>> ins;
+            ins.push_back({cplx(1), cur(isB, t, t, 0)});
+            for (int tg : tags) ins.push_back({cplx(1), cur(isB, t, t, tg)});
+            MatRef dst = work_slot(isB, t, t, 0);
+            cur_cls = isB ? 0 : 1;
+            add(isB ? emitB() : emitA(), dst, ins);
+            cur_cls = 0;
+            (isB ? curB : curA)[key3(t, t, 0)] = dst;
+        }
+    }
+
     void build() {
         Ib = alloc(D.b, D.b);
         Ia = alloc(std::max(D.a, 1), std::max(D.a, 1));
@@ -574,33 +589,40 @@ struct Builder {
         std::vector<StepRec> red;
         if (P > 1) {
             if (arrow) {
-                for (int isB = 0; isB < 2; ++isB) {
-                    std::vector<std::pair<double2, MatRef>> ins;
-                    ins.push_back({cplx(1), cur(isB, t, t, 0)});
-                    for (int p = 0; p < P; ++p) ins.push_back({cplx(1), cur(isB, t, t, p + 1)});
-                    MatRef dst = work_slot(isB, t, t, 0);
-                    cur_cls = isB ? 0 : 1;
-                    add(isB ? emitB() : emitA(), dst, ins);
-                    cur_cls = 0;
-                    (isB ? curB : curA)[key3(t, t, 0)] = dst;
-                }
+                std::vector<int> tags;
+                for (int p = 0; p < P; ++p) tags.push_back(p + 1);
+                sum_tip(tags);
             }
             const auto& R = ps.reduced;
             const size_t m = R.size();
-            if (!arrow && m >= 4) {
-                // The reduced system is itself a BT matrix; it is split like a
-                // two-partition solve: its first half eliminated top-down, its
+            if (m >= 4) {
+                // The reduced system is itself a BT(A) matrix; it is split like
+                // a two-partition solve: its first half eliminated top-down, its
                 // second half bottom-up (concurrently: the halves touch
-                // disjoint blocks and create no fill), then the two middle
-                // blocks in sequence.  Its sequential chain shrinks from m to
-                // m/2 + 1 inverses.  (With an arrowhead both halves would update
-                // the tip, so that case keeps the sequential sweep.)
+                // disjoint blocks and create no fill; each adds its tip
+                // contribution to an accumulator of its own, summed into the
+                // tip afterwards), then the two middle blocks and the tip in
+                // sequence.  Its sequential chain shrinks from m to m/2 + 1
+                // inverses (+ the tip).
                 const size_t h = m / 2;
+                const int tag_top = P + 1, tag_bot = P + 2;
                 std::vector<StepRec> top, bot, mid;
-                for (size_t j = 0; j + 1 < h; ++j) top.push_back(forward(R[j], {R[j + 1]}, 0, true));
-                for (size_t j = m - 1; j > h; --j) bot.push_back(forward(R[j], {R[j - 1]}, 0, true));
-                mid.push_back(forward(R[h - 1], {R[h]}, 0, true));
-                mid.push_back(forward(R[h], {}, 0, true));
+                for (size_t j = 0; j + 1 < h; ++j) {
+                    std::vector<int> N{R[j + 1]};
+                    if (arrow) N.push_back(t);
+                    top.push_back(forward(R[j], N, tag_top, true));
+                }
+                for (size_t j = m - 1; j > h; --j) {
+                    std::vector<int> N{R[j - 1]};
+                    if (arrow) N.push_back(t);
+                    bot.push_back(forward(R[j], N, tag_bot, true));
+                }
+                if (arrow) sum_tip({tag_top, tag_bot});
+                std::vector<int> N1{R[h]}, N2;
+                if (arrow) { N1.push_back(t); N2.push_back(t); }
+                mid.push_back(forward(R[h - 1], N1, 0, true));
+                mid.push_back(forward(R[h], N2, 0, true));
+                if (arrow) mid.push_back(forward(t, {}, 0, true));
                 for (auto it = mid.rbegin(); it != mid.rend(); ++it) backward(*it);
                 for (auto it = top.rbegin(); it != top.rend(); ++it) backward(*it);
                 for (auto it = bot.rbegin(); it != bot.rend(); ++it) backward(*it);

@@ -268,7 +268,7 @@ def test_brute_force_tiny(n, b, a):
     for P in range(1, 5):
         for bounds in _all_bounds(n, P):
             cands.append(oracle.prgf(A, B, bounds))
-            if a == 0 and P >= 3:
+            if P >= 3:
                 cands.append(oracle.prgf(A, B, bounds, reduced_split=True))
     # rounding differs between elimination orders; mistakes give O(1) errors
     for XR, XL in cands:
