@@ -21,7 +21,8 @@
 // effect of the panel on the other columns is M_J = I + Mm Y, where
 //     Mm[:, s] = (panel column s) - e_{p_s}   (d x NB)
 //     Y[s, :]  = W[p_s, :] outside the panel, 0 inside (NB x d),
-// applied by the grouped product kernel as W += Mm Y.
+// applied in the next panel's launch as W += Mm Y: by the panel workgroup to
+// its own block (look-ahead) and by the other workgroups to the rest.
 #include "common.h"
 #include <cfloat>
 #include <climits>

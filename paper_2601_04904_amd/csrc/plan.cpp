@@ -22,7 +22,10 @@
 // write-after-write on whole blocks); all products of one level go into one
 // grouped launch and all inverses of one level into one batched inverse.
 // Independent chains - the B-chain beside the A-chain, partitions beside each
-// other, SQ backward beside SI backward - therefore share launches.
+// other, the two halves of the reduced system, SQ backward beside SI
+// backward - therefore share launches.  The A-chain runs on a second stream;
+// launch lists are compiled once per pointer set (optionally captured as a
+// HIP graph), and product tile shapes come from the tuning table.
 #include "../../include/bt_si_sq.h"
 #include "common.h"
 
