@@ -87,6 +87,16 @@ typedef enum {
                                (captured at its first run, replayed afterwards; not while
                                profiling).  A batch handle uses graphs when every instance
                                sets the flag. */
+#define BT_SIGMA_ANTIHERMITIAN 0x8u
+                            /* the caller asserts Sigma^< = -(Sigma^<)^H on the pattern
+                               (true of the lesser self-energies of NEGF, Sec. II-A).
+                               Every Schur complement of B is then anti-Hermitian, and
+                               the forward sweep takes one block of each conjugate pair
+                               of B updates as the negated conjugate transpose of the
+                               other; the backward sweep takes the k-row products of X^<
+                               from the k-column ones the same way: about a sixth fewer
+                               flops for BT.  The assertion is not checked; for other B
+                               the result is wrong. */
 
 typedef struct {
     int32_t n;                  /* number of diagonal blocks, >= 1 */
@@ -126,7 +136,8 @@ bt_status bt_si_sq_partition_bounds(const bt_desc* desc, int32_t* bounds_out);
 /* Real floating-point operations of one fused SI+SQ solve: `executed` counts
  * the products and inverses the library runs (complex m x n x k product =
  * 8mnk, complex b x b inverse = 8b^3); `useful` counts those of the
- * sequential RGF of the same matrix.  Pure host computation. */
+ * sequential RGF of the same matrix, without BT_SIGMA_ANTIHERMITIAN.  Pure
+ * host computation. */
 bt_status bt_si_sq_flops(const bt_desc* desc, double* executed, double* useful);
 
 /* Validate the descriptor, allocate the workspace, bind the HIP stream

@@ -65,7 +65,7 @@ struct InvJob {
 constexpr int kInvNB = 16;          // panel width (panel rows live in registers)
 constexpr int kInvMaxDim = 1024;    // 512 threads x 2 rows at most
 
-// D = sum_j c_j X_j (elementwise, rows x cols, leading dimensions = cols).
+// D = sum_j c_j op_j(X_j), op_j = X or X^H (elementwise, rows x cols, contiguous).
 constexpr int kMaxAdd = 17;
 struct AddOp {
     double2* D;
@@ -73,7 +73,7 @@ struct AddOp {
     double2 c[kMaxAdd];
     int32_t nin;
     int32_t rows, cols;
-    int32_t pad;
+    uint32_t hmask;       // bit j: input j enters as X_j^H (stored cols x rows; must not be D)
 };
 
 // *out = ||X||_F of one block.

@@ -88,6 +88,7 @@ struct OpRec {
     bool mixed = false;
     int tag = 0;                                   // inverse: block id
     std::vector<std::pair<double2, MatRef>> ins;   // add; norm: (unused, block)
+    uint32_t hmask = 0;                            // add: inputs taken as X^H
     int level = 0;
     int cls = 0;          // 1: critical A-chain stream, 0: main stream
     int wait_other = -1;  // highest level of a predecessor on the other stream
@@ -225,6 +226,7 @@ struct Builder {
     int cur_cls = 0;      // stream class of the operations being emitted
     bool check = false;   // emit the FP64 selected-residual check (mixed path)
     bool plain = false;   // reference schedule: single-term products, one stream
+    bool antiH = false;   // B anti-Hermitian: derive one block of each conjugate pair
     int instance = 0;     // instance id within a batch (reported with singular blocks)
     MatRef Ib, Ia;        // identity blocks (filled once at create)
     MatRef norm_out;      // norms written by the check (5 per block row)
@@ -367,6 +369,22 @@ struct Builder {
         ops.push_back(op);
     }
 
+    // D = sum_j c_j op_j(X_j) with op_j = X_j^H where ins[j].h is set (no
+    // transposed input may be D itself).
+    struct HIn { double2 c; MatRef X; bool h; };
+    void addh(bool emit, MatRef Dst, std::vector<HIn> ins) {
+        if (!emit) return;
+        OpRec op;
+        op.kind = K_ADD;
+        op.D = Dst;
+        op.cls = plain ? 0 : cur_cls;
+        for (size_t j = 0; j < ins.size(); ++j) {
+            op.ins.push_back({ins[j].c, ins[j].X});
+            if (ins[j].h) op.hmask |= 1u << j;
+        }
+        ops.push_back(op);
+    }
+
     int tip_tag(int u, int v, int part_tag) const {
         return (u == D.n && v == D.n) ? part_tag : 0;
     }
@@ -409,15 +427,33 @@ struct Builder {
             r.W[u] = alloc(D.dim(u), dk);
             gemm(emitB(), r.W[u], MatRef{}, zero, {{r.T[u], false, Bkk, false, one}}, mx);
         }
-        for (int u : N)
-            for (int v : N) {
+        for (size_t iu = 0; iu < N.size(); ++iu)
+            for (size_t iv = 0; iv < N.size(); ++iv) {
+                const int u = N[iu], v = N[iv];
                 const int tg = tip_tag(u, v, part_tag);
                 MatRef c = cur(true, u, v, tg);
                 MatRef dst = work_slot(true, u, v, tg);
-                gemm(emitB(), dst, c, one,
-                     {{r.W[u], false, r.T[v], true, one},
-                      {r.T[u], false, r.Bkv[v], false, mone},
-                      {r.Buk[u], false, r.T[v], true, mone}}, mx);
+                if (!antiH) {
+                    gemm(emitB(), dst, c, one,
+                         {{r.W[u], false, r.T[v], true, one},
+                          {r.T[u], false, r.Bkv[v], false, mone},
+                          {r.Buk[u], false, r.T[v], true, mone}}, mx);
+                } else if (iu == iv) {
+                    // B_uk = -B_ku^H, so B_uk T_u^H = -(T_u B_ku)^H: with M = T_u B_ku,
+                    // the update is W_u T_u^H - M + M^H
+                    MatRef M = alloc(D.dim(u), D.dim(u));
+                    gemm(emitB(), M, MatRef{}, zero, {{r.T[u], false, r.Bkv[u], false, one}}, mx);
+                    gemm(emitB(), dst, c, one, {{r.W[u], false, r.T[u], true, one}}, mx);
+                    addh(emitB(), dst, {{one, dst, false}, {mone, M, false}, {one, M, true}});
+                } else if (iu < iv) {
+                    gemm(emitB(), dst, c, one,
+                         {{r.W[u], false, r.T[v], true, one},
+                          {r.T[u], false, r.Bkv[v], false, mone},
+                          {r.Buk[u], false, r.T[v], true, mone}}, mx);
+                } else {
+                    // the updated block (v, u) is formed above: B_uv = -B_vu^H
+                    addh(emitB(), dst, {{mone, curB[key3(v, u, tip_tag(v, u, part_tag))], true}});
+                }
                 curB[key3(u, v, tg)] = dst;
             }
         return r;
@@ -459,12 +495,13 @@ struct Builder {
             for (int w : N) ts.push_back({xloc(false, u, w), false, r.Buk[w], false, one});
             gemm(emitB(), r.GB[u], MatRef{}, zero, ts, mx);
         }
-        for (int v : N) {
-            r.BG[v] = alloc(dk, D.dim(v));
-            std::vector<TermSpec> ts;
-            for (int w : N) ts.push_back({r.Bkv[w], false, xloc(false, v, w), true, one});
-            gemm(emitB(), r.BG[v], MatRef{}, zero, ts, mx);
-        }
+        if (!antiH)
+            for (int v : N) {
+                r.BG[v] = alloc(dk, D.dim(v));
+                std::vector<TermSpec> ts;
+                for (int w : N) ts.push_back({r.Bkv[w], false, xloc(false, v, w), true, one});
+                gemm(emitB(), r.BG[v], MatRef{}, zero, ts, mx);
+            }
         for (int u : N) {
             r.Y21[u] = alloc(D.dim(u), dk);
             gemm(emitB(), r.Y21[u], MatRef{}, zero,
@@ -472,12 +509,18 @@ struct Builder {
         }
         for (int v : N) {
             MatRef L = xloc(true, k, v);
-            gemm(emitB(), L, MatRef{}, zero,
-                 {{r.S, false, r.BG[v], false, one}, {r.SB, false, r.rho[v], true, mone}}, mx);
+            if (!antiH)
+                gemm(emitB(), L, MatRef{}, zero,
+                     {{r.S, false, r.BG[v], false, one}, {r.SB, false, r.rho[v], true, mone}}, mx);
+            else   // S BG_v - S_B rho_v^H = -(Y21_v)^H when B is anti-Hermitian
+                addh(emitB(), L, {{mone, r.Y21[v], true}});
             std::vector<TermSpec> ts;
             for (int w : N) ts.push_back({r.tau[w], false, xloc(true, w, v), false, mone});
             gemm(emitB(), L, L, one, ts, mx);
         }
+        // X^<_{u,k} is computed here even for anti-Hermitian B: taking it as
+        // -(X^<_{k,u})^H couples the errors of the two recurrences and was
+        // measured to amplify rounding by 10^2 - 10^3 on ill-conditioned inputs.
         for (int u : N) {
             std::vector<TermSpec> ts;
             for (int w : N) ts.push_back({xloc(true, u, w), false, r.tau[w], true, mone});
@@ -937,6 +980,7 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                         a.X[q] = o.ins[q].second.p;
                         a.c[q] = o.ins[q].first;
                     }
+                    a.hmask = o.hmask;
                     maxe = std::max(maxe, (size_t)a.rows * a.cols);
                     pg.add.push_back(a);
                     aw = std::max(aw, o.wait_other);
@@ -1134,6 +1178,7 @@ bool build_instances(std::vector<Instance>& inst, const std::vector<int>& sel, M
         bd.mixed_bulk = mixed_handle && !fp64_rerun;
         bd.check = mixed_handle;
         bd.plain = (I.desc.flags & BT_PLAIN) != 0;
+        bd.antiH = (I.desc.flags & BT_SIGMA_ANTIHERMITIAN) != 0;
         bd.instance = i;
         if (!dry) {
             if (A) bd.Aext = A[i];
@@ -1605,6 +1650,7 @@ bt_status bt_si_sq_flops(const bt_desc* desc, double* executed, double* useful) 
     bt_desc seq = *desc;
     seq.partitions = 1;
     seq.part_bounds = nullptr;
+    seq.flags &= ~BT_SIGMA_ANTIHERMITIAN;   // the reference count takes no symmetry
     st = plan_instances(1, &seq, inst, ws, inv, &fu);
     if (st != BT_OK) return st;
     if (executed) *executed = fe;
@@ -2037,6 +2083,7 @@ extern "C" size_t bt_si_sq_diag_schedule(const bt_desc* desc, char* out, size_t 
     bd.bounds = bounds;
     bd.mode = MODE_BOTH;
     bd.mixed_bulk = desc->precision == BT_MIXED;
+    bd.antiH = (desc->flags & BT_SIGMA_ANTIHERMITIAN) != 0;
     bd.ws = reinterpret_cast<char*>((uintptr_t)1 << 40);
     bd.build();
     const int nl = levelize(bd.ops);

@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BT_FP64, BT_GRAPH, BT_MIXED, BT_PLAIN, BTError, check, make_desc
+from ._lib import BT_FP64, BT_GRAPH, BT_MIXED, BT_PLAIN, BT_SIGMA_ANTIHERMITIAN, BTError, check, make_desc
 
 FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
 
@@ -83,9 +83,9 @@ def partition_bounds(n, b, a=0, partitions=1, bounds=None):
     return list(out)
 
 
-def flops(n, b, a=0, partitions=1, bounds=None):
+def flops(n, b, a=0, partitions=1, bounds=None, flags=0):
     """(executed, useful) real flops of one fused SI+SQ solve."""
-    d = make_desc(n, b, a, partitions, bounds)
+    d = make_desc(n, b, a, partitions, bounds, flags=flags)
     ex, us = C.c_double(), C.c_double()
     check(_lib.lib().bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)))
     return ex.value, us.value
@@ -237,7 +237,7 @@ def batch_workspace_bytes(specs) -> int:
 
 
 __all__ = ["DeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
-           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BTError",
+           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN", "BTError",
            "autotune", "tune_table", "set_tune_table"]
 
 

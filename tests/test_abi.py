@@ -162,9 +162,38 @@ def test_header_flag_values_match_binding():
     with open(os.path.join(root, "include", "bt_si_sq.h")) as f:
         text = f.read()
     flags = dict(re.findall(r"#define (BT_[A-Z_]+) (0x[0-9a-f]+)u", text))
-    assert set(flags) == {"BT_DIAG_ONLY", "BT_PLAIN", "BT_GRAPH"}
+    assert set(flags) == {"BT_DIAG_ONLY", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN"}
     for name, val in flags.items():
         assert getattr(_lib, name) == int(val, 16), name
     nums = dict(re.findall(r"#define (BT_TILE_SHAPES|BT_TUNE_SIZE_CLASSES|BT_TUNE_WORK_CLASSES) (\d+)", text))
     for name, val in nums.items():
         assert getattr(_lib, name) == int(val), name
+
+
+@pytest.mark.parametrize("n,b,a", [(1, 8, 0), (16, 32, 0), (64, 512, 0), (5, 7, 3), (128, 384, 512)])
+def test_flop_model_antihermitian(n, b, a):
+    """With BT_SIGMA_ANTIHERMITIAN the sequential op list drops, per eliminated
+    block, the B-update term B_uk T_u^H (diagonal pairs), the three products
+    of every second off-diagonal pair and the k-row products BG_v and
+    S BG_v - S_B rho_v^H (counted independently here); `useful` stays the
+    general count."""
+    from paper_2601_04904_amd import solver as S
+    ex, us = S.flops(n, b, a, flags=_lib.BT_SIGMA_ANTIHERMITIAN)
+    ex0, us0 = S.flops(n, b, a)
+    assert us == us0 == ex0
+
+    def saved(dk, Ns):
+        D = sum(Ns)
+        f = sum(8 * d * d * dk for d in Ns)                                   # diagonal pairs: one term
+        f += sum(3 * 8 * Ns[i] * Ns[j] * dk for i in range(len(Ns)) for j in range(i))   # (v, u), v > u
+        f += 8 * D * D * dk                                                     # BG
+        f += 2 * 8 * dk * dk * D                                                # Y12
+        return f
+
+    ref = 0
+    for k in range(n):
+        Ns = ([b] if k + 1 < n else []) + ([a] if a else [])
+        ref += saved(b, Ns)
+    assert ex == pytest.approx(ex0 - ref, rel=1e-12)
+    if a == 0 and n > 1:
+        assert ex == pytest.approx(160 * (n - 1) * b ** 3 + 24 * b ** 3, rel=1e-12)
