@@ -283,6 +283,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     ap.add_argument("--inflight", type=int, default=2)
     ap.add_argument("--max-wave", type=int, default=8)
+    ap.add_argument("--antihermitian", type=int, default=1,
+                    help="1: also time the reported form with BT_SIGMA_ANTIHERMITIAN (the synthetic "
+                         "Sigma^< is anti-Hermitian) and report it beside the value")
     ap.add_argument("--probe-max-tflop", type=float, default=2.0,
                     help="serving: largest request (TFLOP) spent on probing the mixed path")
     args = ap.parse_args()
@@ -401,6 +404,32 @@ def main():
                                 "p99": round(percentile(t["lat"], 99), 3)})
     compare = {f"P{q}": form_entry(q) for q in forms + extra if q != P}
 
+    # the same form with the anti-Hermitian Sigma^< option (not the value: it
+    # assumes the structure of the input), with its difference to the general path
+    ah = None
+    if args.antihermitian:
+        XLg = XL.to_host()
+        solh = S.Solver(n, b, a, partitions=P, flags=args.flags | S.BT_SIGMA_ANTIHERMITIAN)
+        el_h, lat_h = time_solves(torch, solh, dA, dB, XR, XL, args.steps, args.warmup)
+        ex_h, _ = S.flops(n, b, a, P, flags=S.BT_SIGMA_ANTIHERMITIAN)
+        solh.destroy()
+        XLh = XL.to_host()
+        num = sum(float(np.linalg.norm(getattr(XLh, f) - getattr(XLg, f)) ** 2) for f in S.FIELDS)
+        den = sum(float(np.linalg.norm(getattr(XLg, f)) ** 2) for f in S.FIELDS)
+        sec = el_h / args.steps
+        ah = dict(partitions=P, solves_per_s=round(args.steps / el_h, 4), ms_per_step=round(1e3 * sec, 3),
+                  flops_executed=ex_h, pct_fp64_peak_executed=round(100 * ex_h / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
+                  pct_fp64_peak_useful=round(100 * us / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
+                  latency_ms={"p50": round(percentile(lat_h, 50), 3), "p99": round(percentile(lat_h, 99), 3)},
+                  xl_rel_diff_vs_general=float(np.sqrt(num / max(den, 1e-300))))
+        log(f"[bench] P={P} with BT_SIGMA_ANTIHERMITIAN: {1e3 * sec:.2f} ms/solve, "
+            f"X^< difference to the general path {ah['xl_rel_diff_vs_general']:.2e}")
+        # restore the general path's outputs for the CPU-baseline comparison below
+        sol_g = S.Solver(n, b, a, partitions=P, flags=args.flags)
+        sol_g.solve(dA, dB, XR, XL)
+        sol_g.sync()
+        sol_g.destroy()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -440,6 +469,8 @@ def main():
     }
     if compare:
         out["other_forms"] = compare
+    if ah:
+        out["antihermitian_sigma_form"] = ah
     print(json.dumps(out), flush=True)
     sol.destroy()
 

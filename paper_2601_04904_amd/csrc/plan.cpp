@@ -1931,6 +1931,10 @@ bt_status bt_si_sq_autotune(void* hip_stream, char* report, size_t cap) {
                     if (e == hipSuccess && (best < 0 || ms[sh] < best_ms)) { best = sh; best_ms = ms[sh]; }
                 }
                 if (e != hipSuccess || best < 0) break;
+                // shapes within 3% of the fastest count as ties, broken toward the
+                // larger tile (fewer tiles and launches; keeps repeated tunings stable)
+                for (int sh = kGemmShapes - 1; sh >= 0; --sh)
+                    if (ms[sh] <= 1.03f * best_ms) { best = sh; break; }
                 found[prec][mc][tc] = best;
                 char line[160];
                 snprintf(line, sizeof line, "%d %d %d %d %.1f %.1f %.1f\n", prec, mc, tc, best,
