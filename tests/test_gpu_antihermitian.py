@@ -90,3 +90,31 @@ def test_antihermitian_ill_conditioned_stays_near_general_path(S):
         e0, e1 = rel_err(XL0, L0), rel_err(XL1, L0)
         print(f"P={P}: general {e0:.2e}, anti-Hermitian {e1:.2e}", flush=True)
         assert e1 < max(TOL, 4 * e0)
+
+
+def test_antihermitian_fluctuation_dissipation(S):
+    """B = c(A^H - A) (anti-Hermitian for real c) gives X^< = c(X^R - X^R^H)
+    blockwise: a closed-form check of the flag's path against its own SI."""
+    from paper_2601_04904_amd.synth import equilibrium_B
+    n, b, a = 20, 64, 40
+    A, _ = gen_problem(n, b, a, eta=1e-2, seed=8)
+    c = 0.5
+    B = equilibrium_B(A, c)
+    for P in (1, 4):
+        XR, XL, _ = run(S, A, B, P, flags=S.BT_SIGMA_ANTIHERMITIAN)
+        worst = 0.0
+        for i in range(n):
+            ref = c * (XR.diag[i] - XR.diag[i].conj().T)
+            worst = max(worst, np.linalg.norm(XL.diag[i] - ref) / np.linalg.norm(ref))
+        for i in range(n - 1):
+            ref = c * (XR.upper[i] - XR.lower[i].conj().T)
+            worst = max(worst, np.linalg.norm(XL.upper[i] - ref) / np.linalg.norm(ref))
+            ref = c * (XR.lower[i] - XR.upper[i].conj().T)
+            worst = max(worst, np.linalg.norm(XL.lower[i] - ref) / np.linalg.norm(ref))
+        for i in range(n):
+            ref = c * (XR.arrow_right[i] - XR.arrow_bottom[i].conj().T)
+            worst = max(worst, np.linalg.norm(XL.arrow_right[i] - ref) / np.linalg.norm(ref))
+        ref = c * (XR.tip - XR.tip.conj().T)
+        worst = max(worst, np.linalg.norm(XL.tip - ref) / np.linalg.norm(ref))
+        print(f"P={P}: worst {worst:.2e}", flush=True)
+        assert worst < TOL

@@ -177,3 +177,16 @@ def test_fluctuation_dissipation_on_gpu(S):
     ref = c * (XR.tip - XR.tip.conj().T)
     worst = max(worst, np.linalg.norm(XL.tip - ref) / np.linalg.norm(ref))
     assert worst < TOL
+
+
+@pytest.mark.parametrize("n,b,a,P", [(3, 1024, 0, 1), (2, 1024, 1024, 1), (4, 1000, 24, 2)])
+def test_parity_at_maximum_block_size(S, n, b, a, P):
+    """Blocks at the largest supported size (1024: the inverse kernel's limit)
+    and a ragged size just under it."""
+    print(f"case n={n} b={b} a={a} P={P}", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-2, seed=31 + n + b + a)
+    R0, L0 = oracle.solve_dense(A, B)
+    XR, XL = run_solver(S, A, B, P, None)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    print(f"  err R={eR:.3e} L={eL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL
