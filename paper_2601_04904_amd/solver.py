@@ -92,7 +92,12 @@ def flops(n, b, a=0, partitions=1, bounds=None, flags=0):
 
 
 class Solver:
-    """bt_si_sq_create / _factor / _selected_solve / _solve / _sync / _destroy."""
+    """bt_si_sq_create / _factor / _selected_solve / _solve / _sync / _destroy.
+
+    flags: BT_PLAIN (reference schedule), BT_GRAPH (launch lists replayed as
+    HIP graphs), BT_SIGMA_ANTIHERMITIAN (Sigma^< anti-Hermitian, asserted by
+    the caller and not checked; fewer X^< products).
+    """
 
     def __init__(self, n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, tol=1e-4,
                  stream=None, flags=0):
