@@ -36,7 +36,21 @@ def make_requests(serving, count=10, seed=3):
 
 def test_serving_mix_equals_alone_and_oracle(mods):
     serving, S = mods
-    reqs = make_requests(serving)
+    check_mix(serving, S, make_requests(serving))
+
+
+def test_serving_mix_with_antihermitian_requests(mods):
+    """Requests that assert an anti-Hermitian Sigma^< (every other one) share
+    waves with general ones; each is still the same alone and in the mix."""
+    serving, S = mods
+    reqs = make_requests(serving, count=8, seed=9)
+    for r in reqs:
+        if r.rid % 2:
+            r.flags |= S.BT_SIGMA_ANTIHERMITIAN
+    check_mix(serving, S, reqs)
+
+
+def check_mix(serving, S, reqs):
     eng = serving.ServingEngine(budget_bytes=int(64e9), max_inflight=2, max_wave=4)
     stats = eng.replay(reqs)
     print(stats, "waves", eng.waves, flush=True)
