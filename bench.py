@@ -273,7 +273,7 @@ def main():
                     help="1: run each solve's launch list as a captured HIP graph (BT_GRAPH)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick product tile shapes with the autotuner before timing")
-    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-wave", type=int, default=32)
     ap.add_argument("--plain-count", type=int, default=8)
     ap.add_argument("--requests", type=int, default=24)
