@@ -35,6 +35,12 @@ __device__ inline double2 cmul_i(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// c ? a : b on values (a conditional over two double2 lvalues would select
+// an address and keep the register arrays it points into out of registers)
+__device__ inline double2 sel2(bool c, double2 a, double2 b) {
+    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
+
 // acc += a b and acc -= a b, four fused multiply-adds each
 __device__ inline void cfma(double2& acc, double2 a, double2 b) {
     acc.x = fma(a.x, b.x, acc.x);
@@ -61,44 +67,50 @@ __device__ inline double2 crecip(double2 v) {
     return make_double2(ldexp(a * inv, -e), ldexp(-b * inv, -e));
 }
 
-// Maximum over the 64 lanes of a wave, by DPP moves (both halves of the
-// double): lanes within rows of 16, then row broadcasts; returned to every lane.
+// Maximum of a 32-bit value over the 64 lanes of a wave: DPP steps within
+// rows of 16 lanes, then row broadcasts, after which lane 63 holds the
+// maximum; it is returned to every lane.  Lanes that a broadcast does not
+// reach take 0, the identity of the maximum, so each step is one max with a
+// DPP operand.  The whole wave must be active.
 template <int CTRL, int ROW_MASK>
-__device__ inline double dpp_double(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
-    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
-    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
-    return __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
+__device__ inline unsigned dpp_umax(unsigned x) {
+    return max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false));
 }
 
-__device__ inline double wave_max(double x) {
-    x = fmax(x, dpp_double<0xB1, 0xf>(x));    // quad_perm [1,0,3,2]
-    x = fmax(x, dpp_double<0x4E, 0xf>(x));    // quad_perm [2,3,0,1]
-    x = fmax(x, dpp_double<0x124, 0xf>(x));   // row_ror:4
-    x = fmax(x, dpp_double<0x128, 0xf>(x));   // row_ror:8  -> every lane holds its row's maximum
-    x = fmax(x, dpp_double<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
-    x = fmax(x, dpp_double<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3 -> lane 63 holds it
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+__device__ inline unsigned wave_umax(unsigned x) {
+    x = dpp_umax<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
+    x = dpp_umax<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
+    x = dpp_umax<0x124, 0xf>(x);   // row_ror:4
+    x = dpp_umax<0x128, 0xf>(x);   // row_ror:8  -> every lane holds its row's maximum
+    x = dpp_umax<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_umax<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3 -> lane 63 holds it
+    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Pivot key: |re| + |im| of the candidate (non-finite values clamped to the
-// largest finite double) with the 11 low mantissa bits replaced by
-// 2047 - row.  Non-negative doubles order like their bit patterns, so the
-// largest key is the largest magnitude (to 41 mantissa bits) and, among
-// magnitudes equal to that precision, the lowest row.  No candidate: -1.
-__device__ inline double pivot_key(double2 v, int row) {
+// Maximum of a 64-bit key over the wave: the high words first, then the low
+// words of the lanes whose high word is that maximum.
+__device__ inline unsigned long long wave_max_key(unsigned long long k) {
+    const unsigned hi = (unsigned)(k >> 32);
+    const unsigned h = wave_umax(hi);
+    const unsigned l = wave_umax(hi == h ? (unsigned)k : 0u);
+    return ((unsigned long long)h << 32) | l;
+}
+
+// Pivot key: the bit pattern of |re| + |im| of the candidate (non-finite
+// values clamped to the largest finite double) with the 11 low mantissa bits
+// replaced by 2047 - row.  Non-negative doubles order like their bit
+// patterns, so the largest key is the largest magnitude (to 41 mantissa bits)
+// and, among magnitudes equal to that precision, the lowest row.  Every
+// candidate row is below 1024, so a candidate's key is at least 1024 and 0
+// means "no candidate".
+__device__ inline unsigned long long pivot_key(double2 v, int row) {
     double m = fabs(v.x) + fabs(v.y);
     if (!(m <= DBL_MAX)) m = DBL_MAX;
-    const long long b = (__double_as_longlong(m) & ~2047ll) | (long long)(2047 - row);
-    return __longlong_as_double(b);
+    return ((unsigned long long)__double_as_longlong(m) & ~2047ull) | (unsigned long long)(2047 - row);
 }
 
-__device__ inline int key_row(double key) {
-    return 2047 - (int)(__double_as_longlong(key) & 2047ll);
+__device__ inline int key_row(unsigned long long key) {
+    return 2047 - (int)(key & 2047ull);
 }
 
 // W = src transposed into the column-major working layout, through 16 x 16
@@ -184,7 +196,7 @@ template <int T, int R>
 __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     constexpr int NB = kInvNB;
     constexpr int NW = T / 64;
-    __shared__ double cand_key[2][NW];
+    __shared__ unsigned long long cand_key[2][NW];
     __shared__ double2 cand_ip[2][NW];
     __shared__ double2 cand_row[2][NW][NB];
     __shared__ int piv[NB];
@@ -275,37 +287,41 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
 
     // Candidate of this lane for column s (largest key over its unused rows),
     // the wave maximum, and publication by the lane that holds it: the key,
-    // the reciprocal of its pivot entry and its whole row.
-    double bk, wk;
+    // the reciprocal of its pivot entry and its whole row.  Written with
+    // selects rather than branches, so that the search of a column and the
+    // row updates around it form one block the compiler can interleave.
+    unsigned long long bk, wk;
     double2 bip;
     int bq;
     auto search = [&](auto sc) {
         constexpr int s = decltype(sc)::value;
-        bk = -1.0;
+        bk = 0;
         bq = 0;
         double2 pv = P[0][s];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const double k = used[q] ? -1.0 : pivot_key(P[q][s], tid + q * T);
-            if (k > bk) { bk = k; bq = q; pv = P[q][s]; }
+            const unsigned long long kq = pivot_key(P[q][s], tid + q * T);
+            const unsigned long long k = used[q] ? 0ull : kq;
+            const bool take = k > bk;
+            bk = take ? k : bk;
+            bq = take ? q : bq;
+            pv = sel2(take, P[q][s], pv);
         }
         bip = crecip(pv);
-        wk = wave_max(bk);
+        wk = wave_max_key(bk);
     };
     auto publish = [&](int sb) {
-        if (bk == wk) {
-            if (wk < 0.0) {
-                if (lane == 0) cand_key[sb][wave] = -1.0;
-            } else {
-                cand_key[sb][wave] = wk;
-                cand_ip[sb][wave] = bip;
+        if (wk == 0) {
+            if (lane == 0) cand_key[sb][wave] = 0;
+        } else if (bk == wk) {
+            cand_key[sb][wave] = wk;
+            cand_ip[sb][wave] = bip;
 #pragma unroll
-                for (int q = 0; q < R; ++q)
-                    if (q == bq) {
+            for (int q = 0; q < R; ++q)
+                if (q == bq) {
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) cand_row[sb][wave][c] = P[q][c];
-                    }
-            }
+                    for (int c = 0; c < NB; ++c) cand_row[sb][wave][c] = P[q][c];
+                }
         }
     };
     search(std::integral_constant<int, 0>{});
@@ -313,7 +329,9 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
 
     // Column loop, fully unrolled so that every register index is static.
     // Column s + 1 is updated first, so that its pivot search and reciprocal
-    // overlap the update of the other columns.
+    // overlap the update of the other columns.  Past the last column of a
+    // partial panel every entry is zero, so the update and search of column
+    // s + 1 run unconditionally (their result is not used there).
     //
     // Pivot rows are not rescaled when they are chosen: every row is kept as
     // sc * U, with U in registers and sc = 1 until the row becomes a pivot row,
@@ -330,45 +348,48 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
         constexpr int sb = s & 1;
         if (s >= nc) return;
         __syncthreads();
-        double gk = cand_key[sb][0];
+        unsigned long long gk = cand_key[sb][0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) gk = fmax(gk, cand_key[sb][w]);
-        const int gr = gk < 0.0 ? -1 : key_row(gk);
-        const int gw = gk < 0.0 ? 0 : (gr % T) >> 6;
+        for (int w = 1; w < NW; ++w) {
+            const unsigned long long k = cand_key[sb][w];
+            gk = k > gk ? k : gk;
+        }
+        const int gr = gk == 0 ? -1 : key_row(gk);
+        const int gw = gk == 0 ? 0 : min((gr % T) >> 6, NW - 1);
+        // the winning row's reciprocal pivot and entries, read together
         const double2 ip = cand_ip[sb][gw];
-        bad = bad || gk < 0.0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX) || (ip.x == 0.0 && ip.y == 0.0);
+        double2 v[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v[c] = cand_row[sb][gw][c];
+        bad = bad || gk == 0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX) || (ip.x == 0.0 && ip.y == 0.0);
         double2 g[R];
         bool pr[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             pr[q] = tid + q * T == gr;
             const double2 t = cmul_i(P[q][s], ip);
-            g[q] = pr[q] ? make_double2(0.0, 0.0) : t;
-            if (pr[q]) { used[q] = 1; sc[q] = ip; }
+            g[q] = sel2(pr[q], make_double2(0.0, 0.0), t);
+            used[q] = pr[q] ? 1 : used[q];
+            sc[q] = sel2(pr[q], ip, sc[q]);
         }
         // every other row: U -= (U[s] / pivot) * pivot row, column s + 1 first
-        const bool next = s + 1 < NB && s + 1 < nc;
         if constexpr (s + 1 < NB) {
-            if (next) {
-                const double2 v = cand_row[sb][gw][s + 1];
 #pragma unroll
-                for (int q = 0; q < R; ++q) cfms(P[q][s + 1], g[q], v);
-                search(std::integral_constant<int, s + 1>{});
-            }
+            for (int q = 0; q < R; ++q) cfms(P[q][s + 1], g[q], v[s + 1]);
+            search(std::integral_constant<int, s + 1>{});
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
             if (c == s || c == s + 1) continue;
-            const double2 v = cand_row[sb][gw][c];
 #pragma unroll
-            for (int q = 0; q < R; ++q) cfms(P[q][c], g[q], v);
+            for (int q = 0; q < R; ++q) cfms(P[q][c], g[q], v[c]);
         }
         // the pivot column slot takes -U[s] / pivot, or 1 in the pivot row
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            P[q][s] = pr[q] ? make_double2(1.0, 0.0) : make_double2(-g[q].x, -g[q].y);
+            P[q][s] = sel2(pr[q], make_double2(1.0, 0.0), make_double2(-g[q].x, -g[q].y));
         if (tid == 0) piv[s] = gr < 0 ? 0 : gr;
-        if (next) publish(sb ^ 1);
+        if (s + 1 < nc) publish(sb ^ 1);
     };
     [&]<int... S>(std::integer_sequence<int, S...>) {
         (column(std::integral_constant<int, S>{}), ...);
