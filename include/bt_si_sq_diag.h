@@ -19,7 +19,8 @@ extern "C" {
  * B is stored n x k).  alpha, beta: host arrays {re, im}.  C may be NULL
  * (beta ignored) or equal D.  mixed = 1 runs the product in complex64 on
  * FP32 MFMA (the mixed-precision path).  shape: tile shape 0..BT_TILE_SHAPES-1,
- * or -1 for the one the tuning table gives this launch. */
+ * or -1 for the one the tuning table gives this launch.  Each operand's
+ * stored extent must stay below 2 GiB (BT_ERR_INVALID otherwise). */
 bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
                              const double* alpha, const void* A, int32_t lda, int32_t opA,
                              const void* B, int32_t ldb, int32_t opB,

@@ -80,29 +80,46 @@ __device__ inline int find_op(const GemmOp* __restrict__ ops, int nops, int bid)
     return lo;
 }
 
-// Global -> registers for one stage of term T at k offset k0.  Loads are
-// unconditional (indices clamped into the matrix, out-of-range values replaced
-// by zero afterwards) so that all of a stage's loads are in flight together.
+// Global pointer in the global address space (the C operand's loads).
 #ifdef __HIP_DEVICE_COMPILE__
 typedef const __attribute__((address_space(1))) double2* gptr_t;
 #else
 typedef const double2* gptr_t;
 #endif
 
+// Operand loads go through raw buffer resources, one per operand of the
+// current term: a lane's load address is base + its own 32-bit byte offset +
+// a wave-uniform scalar offset for the stage's k.  A lane whose row, column
+// or k lies outside the operand gets the offset kOOB instead; the record
+// count of every resource (the operand's extent in bytes, below 2^31) is
+// smaller than that, so the hardware returns zeros for it without accessing
+// memory.
+constexpr unsigned kOOB = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format
+
+__device__ inline __amdgpu_buffer_rsrc_t operand_rsrc(const double2* base, int rows, int cols, int ld) {
+    const int extent = ((rows - 1) * ld + cols) * 16;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(base), (short)0, extent, kRsrcWord3);
+}
+
+__device__ inline double2 load_b128(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 // Addressing of one thread's loads for one product term, fixed over all k
-// stages of the term: the pointer to its operand row (A) or column (B) at
-// k = 0, whether that row or column lies inside the matrix, and the element
-// stride between consecutive k.  The term's flags, k and alpha come from the
-// op list in global memory at a uniform address, so they are wave-uniform and
-// the choices on them are scalar.
+// stages of the term: the byte offset of each load at k = 0 (kOOB when its
+// A row or B column lies outside the matrix) and the bytes per unit of k.
+// The term's flags, k and alpha come from the op list in global memory at a
+// uniform address, so they are wave-uniform and the choices on them are
+// scalar.
 template <int BM, int BN>
 struct TermAddr {
     static constexpr int NA = BM * kBK / kThreads;
     static constexpr int NB = BN * kBK / kThreads;
-    gptr_t pa[NA];
-    gptr_t pb[NB];
-    unsigned rowok;       // bit q: A row of load q in range; bit NA + q: B column of load q
-    int ksa, ksb;
+    __amdgpu_buffer_rsrc_t ra, rb;
+    unsigned va[NA];
+    unsigned vb[NB];
+    int ska, skb;
     int km1;
     bool ah, bh;
     int akind;            // alpha: 0 general, 1 exactly +1, 2 exactly -1
@@ -116,6 +133,9 @@ template <int BM> __device__ inline int a_p(bool ah, int e) { return ah ? (e / B
 template <int BN> __device__ inline int b_j(bool bh, int e) { return bh ? (e / kBK) : (e % BN); }
 template <int BN> __device__ inline int b_p(bool bh, int e) { return bh ? (e % kBK) : (e / BN); }
 
+// op(A) is m x k: stored k x m (A^H) or m x k; op(B) is k x n: stored n x k
+// (B^H) or k x n.  Element (i, p) of op(A) sits at p lda + i or i lda + p,
+// element (p, j) of op(B) at j ldb + p or p ldb + j.
 template <int BM, int BN>
 __device__ inline void term_setup(const GemmTerm& T, int m, int n, int i0, int j0, int tid,
                                   TermAddr<BM, BN>& ta) {
@@ -124,62 +144,60 @@ __device__ inline void term_setup(const GemmTerm& T, int m, int n, int i0, int j
     ta.km1 = T.k - 1;
     ta.alpha = T.alpha;
     ta.akind = T.alpha.y != 0.0 ? 0 : T.alpha.x == 1.0 ? 1 : T.alpha.x == -1.0 ? 2 : 0;
-    ta.ksa = ta.ah ? T.lda : 1;
-    ta.ksb = ta.bh ? 1 : T.ldb;
-    ta.rowok = 0;
-    const gptr_t Ap = (gptr_t)T.A;
-    const gptr_t Bp = (gptr_t)T.B;
+    ta.ska = (ta.ah ? T.lda : 1) * 16;
+    ta.skb = (ta.bh ? 1 : T.ldb) * 16;
+    ta.ra = ta.ah ? operand_rsrc(T.A, T.k, m, T.lda) : operand_rsrc(T.A, m, T.k, T.lda);
+    ta.rb = ta.bh ? operand_rsrc(T.B, n, T.k, T.ldb) : operand_rsrc(T.B, T.k, n, T.ldb);
 #pragma unroll
     for (int q = 0; q < ta.NA; ++q) {
-        const int gi = i0 + a_i<BM>(ta.ah, tid + kThreads * q);
-        const int gic = min(gi, m - 1);
-        ta.pa[q] = ta.ah ? Ap + gic : Ap + (size_t)gic * T.lda;
-        ta.rowok |= (gi < m ? 1u : 0u) << q;
+        const int e = tid + kThreads * q;
+        const int gi = i0 + a_i<BM>(ta.ah, e);
+        const unsigned off = (unsigned)((ta.ah ? gi : gi * T.lda) * 16 + a_p<BM>(ta.ah, e) * ta.ska);
+        ta.va[q] = gi < m ? off : kOOB;
     }
 #pragma unroll
     for (int q = 0; q < ta.NB; ++q) {
-        const int gj = j0 + b_j<BN>(ta.bh, tid + kThreads * q);
-        const int gjc = min(gj, n - 1);
-        ta.pb[q] = ta.bh ? Bp + (size_t)gjc * T.ldb : Bp + gjc;
-        ta.rowok |= (gj < n ? 1u : 0u) << (ta.NA + q);
+        const int e = tid + kThreads * q;
+        const int gj = j0 + b_j<BN>(ta.bh, e);
+        const unsigned off = (unsigned)((ta.bh ? gj * T.ldb : gj) * 16 + b_p<BN>(ta.bh, e) * ta.skb);
+        ta.vb[q] = gj < n ? off : kOOB;
     }
 }
 
-// Raw operands of one stage in flight and their in-range flags.
+// Raw operands of one stage in flight.
 template <int BM, int BN>
 struct Stage {
     double2 ra[BM * kBK / kThreads];
     double2 rb[BN * kBK / kThreads];
-    unsigned ok;
 };
 
-// Issue the global loads of one stage at k offset k0.  Loads are
-// unconditional (k clamped into the term; out-of-range values are replaced by
-// zero in finish_stage) so that they are all in flight together and overlap
-// the MFMAs of the current stage.
+// Issue the global loads of one stage at k offset k0, all before any is
+// waited on, so that they overlap the MFMAs of the current stage.  Only the
+// last stage of a term whose k is not a multiple of the stage depth has
+// lanes past k; they are switched to kOOB.
 template <int BM, int BN>
 __device__ inline void issue_stage(const TermAddr<BM, BN>& ta, int k0, int tid, Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
     constexpr int NB = BN * kBK / kThreads;
-    unsigned ok = 0;
+    const int lim = ta.km1 - k0;          // largest k offset inside the term
+    const bool full = lim >= kBK - 1;
+    // wave-uniform by construction; readfirstlane lets the compiler keep them in SGPRs
+    const int soa = __builtin_amdgcn_readfirstlane(k0 * ta.ska);
+    const int sob = __builtin_amdgcn_readfirstlane(k0 * ta.skb);
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-        const int gp = k0 + a_p<BM>(ta.ah, tid + kThreads * q);
-        ok |= (gp <= ta.km1 ? 1u : 0u) << q;
-        st.ra[q] = ta.pa[q][(size_t)min(gp, ta.km1) * ta.ksa];
+        const unsigned vo = full || a_p<BM>(ta.ah, tid + kThreads * q) <= lim ? ta.va[q] : kOOB;
+        st.ra[q] = load_b128(ta.ra, vo, soa);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int gp = k0 + b_p<BN>(ta.bh, tid + kThreads * q);
-        ok |= (gp <= ta.km1 ? 1u : 0u) << (NA + q);
-        st.rb[q] = ta.pb[q][(size_t)min(gp, ta.km1) * ta.ksb];
+        const unsigned vo = full || b_p<BN>(ta.bh, tid + kThreads * q) <= lim ? ta.vb[q] : kOOB;
+        st.rb[q] = load_b128(ta.rb, vo, sob);
     }
-    st.ok = ok & ta.rowok;
 }
 
-// Conjugate, scale by alpha and zero the out-of-range values.  The empty asm
-// consumes every loaded value, so the compiler cannot turn the loads back
-// into conditional ones.
+// Conjugate and scale by alpha (out-of-range values are already zero).  The
+// empty asm consumes every loaded value before any arithmetic on it.
 template <int BM, int BN>
 __device__ inline void finish_stage(const TermAddr<BM, BN>& ta, Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
@@ -188,11 +206,9 @@ __device__ inline void finish_stage(const TermAddr<BM, BN>& ta, Stage<BM, BN>& s
     for (int q = 0; q < NA; ++q) asm volatile("" : "+v"(st.ra[q].x), "+v"(st.ra[q].y));
 #pragma unroll
     for (int q = 0; q < NB; ++q) asm volatile("" : "+v"(st.rb[q].x), "+v"(st.rb[q].y));
+    if (ta.ah) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-        double2 v = st.ra[q];
-        if (ta.ah) v.y = -v.y;
-        st.ra[q] = (st.ok >> q) & 1 ? v : make_double2(0.0, 0.0);
+        for (int q = 0; q < NA; ++q) st.ra[q].y = -st.ra[q].y;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -200,7 +216,7 @@ __device__ inline void finish_stage(const TermAddr<BM, BN>& ta, Stage<BM, BN>& s
         if (ta.bh) v.y = -v.y;
         if (ta.akind == 2) { v.x = -v.x; v.y = -v.y; }
         else if (ta.akind == 0) v = cmul(ta.alpha, v);
-        st.rb[q] = (st.ok >> (NA + q)) & 1 ? v : make_double2(0.0, 0.0);
+        st.rb[q] = v;
     }
 }
 

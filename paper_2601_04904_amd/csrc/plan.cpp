@@ -1980,6 +1980,13 @@ bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
         shape < -1 || shape >= kGemmShapes)
         return set_err(nullptr, BT_ERR_INVALID, "diag_gemm: bad arguments");
     if (m == 0 || n == 0) return BT_OK;
+    if (k > 0) {
+        // the product kernel addresses each operand with 32-bit byte offsets
+        const long long extA = opA ? (long long)(k - 1) * lda + m : (long long)(m - 1) * lda + k;
+        const long long extB = opB ? (long long)(n - 1) * ldb + k : (long long)(k - 1) * ldb + n;
+        if (extA * 16 >= (1ll << 31) || extB * 16 >= (1ll << 31))
+            return set_err(nullptr, BT_ERR_INVALID, "diag_gemm: operands of 2 GiB or more are not supported");
+    }
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     GemmOp g;
     memset(&g, 0, sizeof g);
