@@ -106,6 +106,14 @@ __device__ inline double2 load_b128(__amdgpu_buffer_rsrc_t r, unsigned voff, int
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// What a stage's operands need between load and LDS: conjugation of A and
+// B, and alpha (folded into B).  Taken from the term, so wave-uniform.
+struct StageFlags {
+    bool ah, bh;
+    int akind;            // alpha: 0 general, 1 exactly +1, 2 exactly -1
+    double2 alpha;
+};
+
 // Addressing of one thread's loads for one product term, fixed over all k
 // stages of the term: the byte offset of each load at k = 0 (kOOB when its
 // A row or B column lies outside the matrix) and the bytes per unit of k.
@@ -121,9 +129,7 @@ struct TermAddr {
     unsigned vb[NB];
     int ska, skb;
     int km1;
-    bool ah, bh;
-    int akind;            // alpha: 0 general, 1 exactly +1, 2 exactly -1
-    double2 alpha;
+    StageFlags f;
 };
 
 // Coordinates of load e (= tid + kThreads q) inside the stage tile: A (i, p)
@@ -139,27 +145,28 @@ template <int BN> __device__ inline int b_p(bool bh, int e) { return bh ? (e % k
 template <int BM, int BN>
 __device__ inline void term_setup(const GemmTerm& T, int m, int n, int i0, int j0, int tid,
                                   TermAddr<BM, BN>& ta) {
-    ta.ah = T.flags & kTermAH;
-    ta.bh = T.flags & kTermBH;
+    const bool ah = T.flags & kTermAH, bh = T.flags & kTermBH;
+    ta.f.ah = ah;
+    ta.f.bh = bh;
+    ta.f.alpha = T.alpha;
+    ta.f.akind = T.alpha.y != 0.0 ? 0 : T.alpha.x == 1.0 ? 1 : T.alpha.x == -1.0 ? 2 : 0;
     ta.km1 = T.k - 1;
-    ta.alpha = T.alpha;
-    ta.akind = T.alpha.y != 0.0 ? 0 : T.alpha.x == 1.0 ? 1 : T.alpha.x == -1.0 ? 2 : 0;
-    ta.ska = (ta.ah ? T.lda : 1) * 16;
-    ta.skb = (ta.bh ? 1 : T.ldb) * 16;
-    ta.ra = ta.ah ? operand_rsrc(T.A, T.k, m, T.lda) : operand_rsrc(T.A, m, T.k, T.lda);
-    ta.rb = ta.bh ? operand_rsrc(T.B, n, T.k, T.ldb) : operand_rsrc(T.B, T.k, n, T.ldb);
+    ta.ska = (ah ? T.lda : 1) * 16;
+    ta.skb = (bh ? 1 : T.ldb) * 16;
+    ta.ra = ah ? operand_rsrc(T.A, T.k, m, T.lda) : operand_rsrc(T.A, m, T.k, T.lda);
+    ta.rb = bh ? operand_rsrc(T.B, n, T.k, T.ldb) : operand_rsrc(T.B, T.k, n, T.ldb);
 #pragma unroll
     for (int q = 0; q < ta.NA; ++q) {
         const int e = tid + kThreads * q;
-        const int gi = i0 + a_i<BM>(ta.ah, e);
-        const unsigned off = (unsigned)((ta.ah ? gi : gi * T.lda) * 16 + a_p<BM>(ta.ah, e) * ta.ska);
+        const int gi = i0 + a_i<BM>(ah, e);
+        const unsigned off = (unsigned)((ah ? gi : gi * T.lda) * 16 + a_p<BM>(ah, e) * ta.ska);
         ta.va[q] = gi < m ? off : kOOB;
     }
 #pragma unroll
     for (int q = 0; q < ta.NB; ++q) {
         const int e = tid + kThreads * q;
-        const int gj = j0 + b_j<BN>(ta.bh, e);
-        const unsigned off = (unsigned)((ta.bh ? gj * T.ldb : gj) * 16 + b_p<BN>(ta.bh, e) * ta.skb);
+        const int gj = j0 + b_j<BN>(bh, e);
+        const unsigned off = (unsigned)((bh ? gj * T.ldb : gj) * 16 + b_p<BN>(bh, e) * ta.skb);
         ta.vb[q] = gj < n ? off : kOOB;
     }
 }
@@ -174,54 +181,63 @@ struct Stage {
 // Issue the global loads of one stage at k offset k0, all before any is
 // waited on, so that they overlap the MFMAs of the current stage.  Only the
 // last stage of a term whose k is not a multiple of the stage depth has
-// lanes past k; they are switched to kOOB.
+// lanes past k; they are switched to kOOB.  With live false every lane is
+// switched to kOOB: the register set is then defined (all zeros) without
+// any memory access, so the caller can issue unconditionally and the
+// compiler never has to keep a register set's old and new values at once.
 template <int BM, int BN>
-__device__ inline void issue_stage(const TermAddr<BM, BN>& ta, int k0, int tid, Stage<BM, BN>& st) {
+__device__ inline void issue_stage(const TermAddr<BM, BN>& ta, int k0, int tid, Stage<BM, BN>& st,
+                                   bool live = true) {
     constexpr int NA = BM * kBK / kThreads;
     constexpr int NB = BN * kBK / kThreads;
-    const int lim = ta.km1 - k0;          // largest k offset inside the term
+    const int lim = live ? ta.km1 - k0 : -1;   // largest k offset inside the term
     const bool full = lim >= kBK - 1;
     // wave-uniform by construction; readfirstlane lets the compiler keep them in SGPRs
-    const int soa = __builtin_amdgcn_readfirstlane(k0 * ta.ska);
-    const int sob = __builtin_amdgcn_readfirstlane(k0 * ta.skb);
+    const int soa = __builtin_amdgcn_readfirstlane(live ? k0 * ta.ska : 0);
+    const int sob = __builtin_amdgcn_readfirstlane(live ? k0 * ta.skb : 0);
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-        const unsigned vo = full || a_p<BM>(ta.ah, tid + kThreads * q) <= lim ? ta.va[q] : kOOB;
+        const unsigned vo = full || a_p<BM>(ta.f.ah, tid + kThreads * q) <= lim ? ta.va[q] : kOOB;
         st.ra[q] = load_b128(ta.ra, vo, soa);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const unsigned vo = full || b_p<BN>(ta.bh, tid + kThreads * q) <= lim ? ta.vb[q] : kOOB;
+        const unsigned vo = full || b_p<BN>(ta.f.bh, tid + kThreads * q) <= lim ? ta.vb[q] : kOOB;
         st.rb[q] = load_b128(ta.rb, vo, sob);
     }
 }
 
-// Conjugate and scale by alpha (out-of-range values are already zero).  The
-// empty asm consumes every loaded value before any arithmetic on it.
+// Conjugate and scale by alpha (out-of-range values are already zero).
+// Conjugation and alpha = -1 are sign flips with wave-uniform masks, so the
+// common case has no branch; only a general alpha takes the complex product.
+__device__ inline double flip_sign(double v, unsigned long long mask) {
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)mask);
+}
+
 template <int BM, int BN>
-__device__ inline void finish_stage(const TermAddr<BM, BN>& ta, Stage<BM, BN>& st) {
+__device__ inline void finish_stage(const StageFlags& f, Stage<BM, BN>& st) {
     constexpr int NA = BM * kBK / kThreads;
     constexpr int NB = BN * kBK / kThreads;
+    constexpr unsigned long long kSign = 0x8000000000000000ull;
+    const bool neg = f.akind == 2;
+    const unsigned long long ma = f.ah ? kSign : 0ull;             // Im A
+    const unsigned long long mbx = neg ? kSign : 0ull;             // Re B
+    const unsigned long long mby = f.bh != neg ? kSign : 0ull;     // Im B
 #pragma unroll
-    for (int q = 0; q < NA; ++q) asm volatile("" : "+v"(st.ra[q].x), "+v"(st.ra[q].y));
-#pragma unroll
-    for (int q = 0; q < NB; ++q) asm volatile("" : "+v"(st.rb[q].x), "+v"(st.rb[q].y));
-    if (ta.ah) {
-#pragma unroll
-        for (int q = 0; q < NA; ++q) st.ra[q].y = -st.ra[q].y;
-    }
+    for (int q = 0; q < NA; ++q) st.ra[q].y = flip_sign(st.ra[q].y, ma);
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        double2 v = st.rb[q];
-        if (ta.bh) v.y = -v.y;
-        if (ta.akind == 2) { v.x = -v.x; v.y = -v.y; }
-        else if (ta.akind == 0) v = cmul(ta.alpha, v);
-        st.rb[q] = v;
+        st.rb[q].x = flip_sign(st.rb[q].x, mbx);
+        st.rb[q].y = flip_sign(st.rb[q].y, mby);
+    }
+    if (f.akind == 0) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) st.rb[q] = cmul(f.alpha, st.rb[q]);
     }
 }
 
 template <bool MIXED, int BM, int BN>
-__device__ inline void store_stage(const TermAddr<BM, BN>& ta, int tid, const Stage<BM, BN>& st,
+__device__ inline void store_stage(const StageFlags& ta, int tid, const Stage<BM, BN>& st,
                                    typename Prec<MIXED>::C (*As)[BM + 1],
                                    typename Prec<MIXED>::C (*Bs)[BN + 1]) {
     constexpr int NA = BM * kBK / kThreads;
@@ -309,10 +325,12 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
 
     // Stages are (term, k offset) pairs in order; next() steps to the
     // following one, skipping empty terms.  Two register sets hold the raw
-    // operands of the next two stages, so within a term the global loads of
-    // a stage are issued two stages ahead of its MFMAs; at a term boundary
-    // the new term's first stage is issued one stage ahead (the addressing
-    // `ta` describes one term at a time).
+    // operands of the next two stages: each step first issues the loads of
+    // the stage after next (setting up that stage's term when it starts a
+    // new one), then runs the MFMAs of the stage in LDS, then converts the
+    // next stage's operands (waiting for their loads) into the other LDS
+    // buffer.  Each register set carries the flags of the term it was
+    // loaded for.
     auto next = [&](int& t, int& k0) {
         k0 += kBK;
         while (t < nterms && k0 >= terms[t].k) { ++t; k0 = 0; }
@@ -320,6 +338,7 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
     int t1 = 0, k1 = 0;
     while (t1 < nterms && terms[t1].k <= 0) ++t1;
     Stage<BM, BN> st[2];
+    StageFlags sf[2];
     TermAddr<BM, BN> ta;
     int ta_term = -1;
     bool cur = false, fly = false;
@@ -327,15 +346,14 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
         term_setup<BM, BN>(terms[t1], m, n, i0, j0, tid, ta);
         ta_term = t1;
         issue_stage<BM, BN>(ta, k1, tid, st[0]);
-        finish_stage<BM, BN>(ta, st[0]);
-        store_stage<MIXED, BM, BN>(ta, tid, st[0], As[0], Bs[0]);
+        finish_stage<BM, BN>(ta.f, st[0]);
+        store_stage<MIXED, BM, BN>(ta.f, tid, st[0], As[0], Bs[0]);
         cur = true;
         next(t1, k1);
-        if (t1 < nterms) {
-            if (t1 != ta_term) { term_setup<BM, BN>(terms[t1], m, n, i0, j0, tid, ta); ta_term = t1; }
-            issue_stage<BM, BN>(ta, k1, tid, st[1]);
-            fly = true;
-        }
+        fly = t1 < nterms;
+        if (fly && t1 != ta_term) { term_setup<BM, BN>(terms[t1], m, n, i0, j0, tid, ta); ta_term = t1; }
+        issue_stage<BM, BN>(ta, k1, tid, st[1], fly);
+        sf[1] = ta.f;
     }
     __syncthreads();
     int buf = 0;
@@ -349,8 +367,12 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
             next(t2, k2);
             fly2 = t2 < nterms;
         }
-        const bool early = fly2 && t2 == ta_term;
-        if (early) issue_stage<BM, BN>(ta, k2, tid, st[Y]);
+        if (fly2 && t2 != ta_term) { term_setup<BM, BN>(terms[t2], m, n, i0, j0, tid, ta); ta_term = t2; }
+        issue_stage<BM, BN>(ta, k2, tid, st[Y], fly2);
+        sf[Y] = ta.f;
+        // keep the order issue -> MFMAs -> conversion of the next stage, so
+        // that the loads in flight have a whole stage of MFMAs to land
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kk = 0; kk < kBK / 2; ++kk) {
             const int p = 2 * kk + pOff;
@@ -374,15 +396,11 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
                 for (int ni = 0; ni < NI; ++ni)
                     acc[g][ni] = Prec<MIXED>::mfma(av[g], bv[ni], acc[g][ni]);
         }
-        if (fly) {
-            finish_stage<BM, BN>(ta, st[X]);
-            store_stage<MIXED, BM, BN>(ta, tid, st[X], As[buf ^ 1], Bs[buf ^ 1]);
-        }
-        if (fly2 && !early) {
-            term_setup<BM, BN>(terms[t2], m, n, i0, j0, tid, ta);
-            ta_term = t2;
-            issue_stage<BM, BN>(ta, k2, tid, st[Y]);
-        }
+        __builtin_amdgcn_sched_barrier(0);
+        // unconditional like the issue: without a next stage st[X] holds
+        // zeros from kOOB loads, stored to the buffer no later stage reads
+        finish_stage<BM, BN>(sf[X], st[X]);
+        store_stage<MIXED, BM, BN>(sf[X], tid, st[X], As[buf ^ 1], Bs[buf ^ 1]);
         __syncthreads();
         cur = fly;
         fly = fly2;
