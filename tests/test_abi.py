@@ -197,3 +197,22 @@ def test_flop_model_antihermitian(n, b, a):
     assert ex == pytest.approx(ex0 - ref, rel=1e-12)
     if a == 0 and n > 1:
         assert ex == pytest.approx(160 * (n - 1) * b ** 3 + 24 * b ** 3, rel=1e-12)
+
+
+@pytest.mark.parametrize("opA,opB,big", [(0, 0, "A"), (1, 0, "A"), (0, 1, "B"), (0, 0, "B")])
+def test_diag_gemm_rejects_operands_past_32bit_offsets(opA, opB, big):
+    """The product kernel addresses each operand with 32-bit byte offsets, so
+    the diagnostic entry refuses an operand whose stored extent reaches 2 GiB.
+    The check runs before any device call (the pointers are never touched)."""
+    L = _lib.lib()
+    one = (C.c_double * 2)(1.0, 0.0)
+    zero = (C.c_double * 2)(0.0, 0.0)
+    m = n = k = 64
+    huge = 1 << 25                       # 64 rows x 2^25 elements x 16 B > 2 GiB
+    lda = huge if big == "A" else 64
+    ldb = huge if big == "B" else 64
+    dummy = C.c_void_p(16)
+    st = L.bt_si_sq_diag_gemm(m, n, k, one, dummy, lda, opA, dummy, ldb, opB,
+                              zero, None, 64, dummy, 64, 0, -1, None)
+    assert st == BT_ERR_INVALID
+    assert b"2 GiB" in L.bt_si_sq_last_error(None)
