@@ -408,10 +408,20 @@ void zgemm_grouped(const GemmOp* __restrict__ ops, int nops) {
         k1 = k2;
         buf ^= 1;
     };
+    // FP64: four steps per iteration.  The compiler's wait counts throttle
+    // the load issue only in the first bodies after the loop header, so the
+    // longer body keeps the loads two stages ahead in the others.  (The mixed
+    // kernels keep two: four would cost them occupancy.)
     while (cur) {
         step(std::integral_constant<int, 1>{});
         if (!cur) break;
         step(std::integral_constant<int, 0>{});
+        if constexpr (!MIXED) {
+            if (!cur) break;
+            step(std::integral_constant<int, 1>{});
+            if (!cur) break;
+            step(std::integral_constant<int, 0>{});
+        }
     }
 
     // Epilogue: lane holds real column lane%16 (component lane%2 of complex
