@@ -93,7 +93,9 @@ typedef const double2* gptr_t;
 // or k lies outside the operand gets the offset kOOB instead; the record
 // count of every resource (the operand's extent in bytes, below 2^31) is
 // smaller than that, so the hardware returns zeros for it without accessing
-// memory.
+// memory.  For every other lane the byte offset plus the scalar offset stays
+// inside the operand, so no access leaves it whether or not the hardware's
+// range check counts the scalar offset.
 constexpr unsigned kOOB = 0x80000000u;
 constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format
 
