@@ -38,6 +38,20 @@ def percentile(xs, q):
     return xs[i]
 
 
+def latency_summary(xs):
+    """Per-solve times in ms: p50 and p99, the mean, and the half-width of the
+    mean's 95% confidence interval (Student t over the timed solves)."""
+    n = len(xs)
+    mean = sum(xs) / n
+    out = {"p50": round(percentile(xs, 50), 3), "p99": round(percentile(xs, 99), 3),
+           "mean": round(mean, 3)}
+    if n > 1:
+        from scipy.stats import t as student_t
+        sd = (sum((x - mean) ** 2 for x in xs) / (n - 1)) ** 0.5
+        out["ci95"] = round(float(student_t.ppf(0.975, n - 1)) * sd / n ** 0.5, 3)
+    return out
+
+
 def time_solves(torch, sol, dA, dB, XR, XL, steps, warmup):
     for _ in range(warmup):
         sol.solve(dA, dB, XR, XL)
@@ -400,8 +414,7 @@ def main():
                     ms_per_step=round(1e3 * sec, 3), launches=t["launches"],
                     pct_fp64_peak_executed=round(100 * t["ex"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
                     pct_fp64_peak_useful=round(100 * t["us"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
-                    latency_ms={"p50": round(percentile(t["lat"], 50), 3),
-                                "p99": round(percentile(t["lat"], 99), 3)})
+                    latency_ms=latency_summary(t["lat"]))
     compare = {f"P{q}": form_entry(q) for q in forms + extra if q != P}
 
     # the same form with the anti-Hermitian Sigma^< option (not the value: it
@@ -420,7 +433,7 @@ def main():
         ah = dict(partitions=P, solves_per_s=round(args.steps / el_h, 4), ms_per_step=round(1e3 * sec, 3),
                   flops_executed=ex_h, pct_fp64_peak_executed=round(100 * ex_h / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
                   pct_fp64_peak_useful=round(100 * us / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
-                  latency_ms={"p50": round(percentile(lat_h, 50), 3), "p99": round(percentile(lat_h, 99), 3)},
+                  latency_ms=latency_summary(lat_h),
                   xl_rel_diff_vs_general=float(np.sqrt(num / max(den, 1e-300))))
         log(f"[bench] P={P} with BT_SIGMA_ANTIHERMITIAN: {1e3 * sec:.2f} ms/solve, "
             f"X^< difference to the general path {ah['xl_rel_diff_vs_general']:.2e}")
@@ -461,7 +474,7 @@ def main():
         "tflops_useful": round(tflops_us, 3),
         "pct_fp64_peak_executed": round(100 * tflops_ex / FP64_PEAK_TFLOPS, 2),
         "pct_fp64_peak_useful": round(100 * tflops_us / FP64_PEAK_TFLOPS, 2),
-        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
+        "latency_ms": latency_summary(lat),
         "launches_per_solve": launches,
         "kernel_ms_per_solve": kernel_share,
         "roofline": roof,
