@@ -54,6 +54,11 @@ CASES = [
     (12, 24, 20, 3, None),
     (10, 33, 65, 4, [0, 2, 4, 6, 10]),
     (6, 70, 17, 2, [0, 1, 6]),
+    # reduced systems of 16 to 30 blocks (long halves in the reduced solve)
+    (24, 16, 0, 9, None),
+    (18, 9, 5, 9, [0, 1, 3, 5, 7, 9, 11, 13, 15, 18]),
+    (30, 12, 20, 12, None),
+    (40, 8, 12, 16, None),
 ]
 
 
