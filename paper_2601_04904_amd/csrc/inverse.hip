@@ -206,6 +206,9 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     const int d = J.d;
     const int j0 = p * NB;
     if (j0 >= d) return;
+    // the panel is the critical path of the launch: its waves win instruction
+    // issue over the update workgroups and other kernels' waves on the CU
+    __builtin_amdgcn_s_setprio(3);
     const int nc = min(NB, d - j0);
     const int lane = tid & 63, wave = tid >> 6;
 
