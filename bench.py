@@ -254,8 +254,10 @@ def bench_serve(args, torch, S):
     peng = serving.ServingEngine(budget_bytes=budget, max_inflight=1, max_wave=1)
     pstats = peng.replay(plain_reqs)
     log(f"[bench] plain RGF serving: {pstats}")
+    # a run in which any wave failed has no valid throughput
+    value = round(stats["solves_per_s"], 4) if not eng.errors and not stats.get("failed") else None
     out = {
-        "metric": METRIC, "value": round(stats["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * stats["wall_s"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
         "data": "synthetic",

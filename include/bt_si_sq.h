@@ -68,7 +68,8 @@ typedef enum {
     BT_ERR_SINGULAR = 3,    /* zero or non-finite pivot in a diagonal-block inverse */
     BT_ERR_HIP = 4,         /* a HIP runtime call failed */
     BT_ERR_STATE = 5,       /* e.g. selected_solve before factor */
-    BT_ERR_TOLERANCE = 6    /* reserved */
+    BT_ERR_TOLERANCE = 6    /* mixed path: the error estimate of the FP64 re-run is still
+                               above tol; the results and estimates are written */
 } bt_status;
 
 typedef enum {
@@ -163,8 +164,11 @@ bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR);
  *     rho_L = max_i ||R^<_i||_F / (nA max_i ||X^<_ii||_F),
  *     nA = max_i ||A_ii||_F / sqrt(d_i),  nG = max_i ||X^R_ii||_F
  * (a relative residual times a blockwise ||A|| ||A^-1|| estimate), and when
- * it exceeds tol re-runs the whole solve with FP64 products, returning the
- * estimate of the final result and used_fp64_fallback = 1. */
+ * it exceeds tol re-runs the whole solve with FP64 products - factor and
+ * selected solve of the A and X^R given to the last factor call, so an error
+ * that comes from the A-chain is removed too - returning the estimate of the
+ * final result and used_fp64_fallback = 1.  If that estimate is still above
+ * tol the call returns BT_ERR_TOLERANCE (results and estimate written). */
 bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_blocks* XL,
                                   double* err_estimate, int* used_fp64_fallback);
 
@@ -182,7 +186,9 @@ bt_status bt_si_sq_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_blocks*
  * instances share one grouped launch and their diagonal-block inverses one
  * batched inverse, so many small solves fill the GPU together.  Mixed
  * instances get their error estimate and, above their tol, an FP64 re-run
- * of just those instances (the call then waits for the stream). */
+ * of just those instances (the call then waits for the stream);
+ * BT_ERR_TOLERANCE when a re-run instance's estimate is still above its tol
+ * (every result and estimate written). */
 size_t bt_si_sq_batch_workspace_bytes(int32_t count, const bt_desc* descs);
 
 bt_status bt_si_sq_batch_create(int32_t count, const bt_desc* descs, void* hip_stream,

@@ -55,6 +55,17 @@ class BTError(RuntimeError):
         self.status = status
 
 
+class BTToleranceError(BTError):
+    """BT_ERR_TOLERANCE: the FP64 re-run of a mixed-precision solve still has an
+    error estimate above tol.  The results are written; err and fallback hold
+    the estimates and fallback flags the call returned."""
+
+    def __init__(self, msg: str, err, fallback):
+        super().__init__(BT_ERR_TOLERANCE, msg)
+        self.err = err
+        self.fallback = fallback
+
+
 _lib = None
 
 
@@ -140,6 +151,15 @@ def make_desc(n: int, b: int, a: int = 0, partitions: int = 1, bounds=None,
     d.precision, d.tol, d.flags = precision, tol, flags
     d._keep = keep  # keep the bounds array alive with the descriptor
     return d
+
+
+def check_tol(status: int, handle, err, fallback):
+    """check(), except that BT_ERR_TOLERANCE raises BTToleranceError with the
+    call's estimates and fallback flags attached."""
+    if status == BT_ERR_TOLERANCE:
+        msg = lib().bt_si_sq_last_error(handle)
+        raise BTToleranceError(msg.decode() if msg else "", err, fallback)
+    check(status, handle)
 
 
 def check(status: int, handle=None):

@@ -358,15 +358,27 @@ struct Builder {
         ops.push_back(op);
     }
 
+    // D = sum_j c_j X_j.  One sum takes at most kMaxAdd inputs; longer sums
+    // (the tip of more than kMaxAdd - 1 partitions) are chained: the first
+    // part writes D, each later part adds kMaxAdd - 1 more inputs to D.
     void add(bool emit, MatRef Dst, std::vector<std::pair<double2, MatRef>> ins) {
         if (!emit) return;
-        OpRec op;
-        op.kind = K_ADD;
-        op.D = Dst;
-        op.cls = plain ? 0 : cur_cls;
+        std::vector<std::pair<double2, MatRef>> kept;
         for (auto& x : ins)
-            if (x.second.ok()) op.ins.push_back(x);
-        ops.push_back(op);
+            if (x.second.ok()) kept.push_back(x);
+        size_t i = 0;
+        bool first = true;
+        do {
+            OpRec op;
+            op.kind = K_ADD;
+            op.D = Dst;
+            op.cls = plain ? 0 : cur_cls;
+            if (!first) op.ins.push_back({cplx(1), Dst});
+            const size_t room = first ? (size_t)kMaxAdd : (size_t)kMaxAdd - 1;
+            for (size_t q = 0; q < room && i < kept.size(); ++q, ++i) op.ins.push_back(kept[i]);
+            ops.push_back(op);
+            first = false;
+        } while (i < kept.size());
     }
 
     // D = sum_j c_j op_j(X_j) with op_j = X_j^H where ins[j].h is set (no
@@ -792,6 +804,7 @@ struct Program {
     double flops = 0.0;
     int levels = 0;
     int n_events = 0;               // cross-stream events the launches use
+    std::string error;              // non-empty: the operation list cannot be launched
 };
 
 GemmOp make_gemm_op(const OpRec& o) {
@@ -970,13 +983,17 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                 for (int i : bylevel[L]) {
                     const OpRec& o = ops[i];
                     if (o.kind != K_ADD || o.cls != cls) continue;
+                    if (o.ins.size() > (size_t)kMaxAdd) {
+                        pg.error = "internal: a block sum has more than 17 inputs";
+                        return pg;
+                    }
                     AddOp a;
                     memset(&a, 0, sizeof a);
                     a.D = o.D.p;
                     a.nin = (int)o.ins.size();
                     a.rows = o.D.r;
                     a.cols = o.D.c;
-                    for (int q = 0; q < a.nin && q < kMaxAdd; ++q) {
+                    for (int q = 0; q < a.nin; ++q) {
                         a.X[q] = o.ins[q].second.p;
                         a.c[q] = o.ins[q].first;
                     }
@@ -1379,6 +1396,7 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& s
         for (int i : sel) plain = plain && (h->inst[i].desc.flags & BT_PLAIN);
         int nl = levelize(bt.ops, plain);
         Program pg = compile(bt.ops, nl, h->inv_pool);
+        if (!pg.error.empty()) return set_err(h, BT_ERR_INVALID, pg.error);
         if (pg.inv_scratch_bytes > h->inv_bytes)
             return set_err(h, BT_ERR_INVALID, "internal: inverse scratch too small");
         pg.flops = bt.flops;
@@ -1503,13 +1521,26 @@ bt_status run_instances(bt_si_sq_plan* h, Mode mode, const std::vector<int>& sel
         if (err) err[sel[q]] = est[q];
     }
     if (redo.empty()) return BT_OK;
-    st = prepare_and_run(h, mode, redo, A, B, XR, XL, true, &c);
+    // The re-run repeats the whole solve with FP64 products: after a mixed
+    // factor the stored S, T and X^R carry FP32 rounding, so a selected solve
+    // alone (MODE_SQ) on them could not remove an error that comes from the
+    // A-chain.  A and X^R are the ones the factor call used.
+    st = prepare_and_run(h, MODE_BOTH, redo, A, B, XR, XL, true, &c);
     if (st != BT_OK) return st;
     st = read_estimates(h, *c, est);
     if (st != BT_OK) return st;
+    int above = -1;
     for (size_t q = 0; q < redo.size(); ++q) {
         if (err) err[redo[q]] = est[q];
         if (fb) fb[redo[q]] = 1;
+        if (above < 0 && est[q] > h->inst[redo[q]].desc.tol) above = redo[q];
+    }
+    if (above >= 0) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "instance %d: error estimate %.3e of the FP64 re-run is above tol %.3e "
+                 "(results written)", above, est[std::find(redo.begin(), redo.end(), above) - redo.begin()],
+                 h->inst[above].desc.tol);
+        return set_err(h, BT_ERR_TOLERANCE, buf);
     }
     return BT_OK;
 }
@@ -1566,6 +1597,7 @@ bt_status plan_instances(int count, const bt_desc* descs, std::vector<Instance>&
     for (auto& I : inst) plain = plain && (I.desc.flags & BT_PLAIN);
     int nl = levelize(bt.ops, plain);
     Program pg = compile(bt.ops, nl, reinterpret_cast<char*>((uintptr_t)3 << 40));
+    if (!pg.error.empty()) return set_err(nullptr, BT_ERR_INVALID, pg.error);
     inv_bytes = pg.inv_scratch_bytes;
     return BT_OK;
 }
@@ -1725,7 +1757,7 @@ bt_status bt_si_sq_batch_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_b
     std::vector<int> sel(count);
     for (int i = 0; i < count; ++i) sel[i] = i;
     bt_status st = run_instances(h, MODE_BOTH, sel, A, B, XR, XL, err_estimates, used_fp64_fallback);
-    if (st == BT_OK)
+    if (st == BT_OK || st == BT_ERR_TOLERANCE)   // results written either way
         for (int i = 0; i < count; ++i) {
             h->inst[i].factored = true;
             h->inst[i].A_used = A[i];

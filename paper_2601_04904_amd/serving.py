@@ -206,6 +206,7 @@ class ServingEngine:
     def _run_wave(self, wave):
         torch = self.torch
         stream = torch.cuda.Stream()
+        bs = None
         try:
             with torch.cuda.stream(stream):
                 t_start = self.now()
@@ -233,6 +234,7 @@ class ServingEngine:
                 bs.sync()
                 t_done = self.now()
                 bs.destroy()
+                bs = None
                 if self.router is not None:
                     for i, r in enumerate(wave):
                         if r.spec()["precision"] == S.BT_MIXED:
@@ -246,7 +248,14 @@ class ServingEngine:
                 del inputs
         except Exception as ex:  # keep the loop alive; report at the end
             self.errors.append(repr(ex))
+            for r in wave:
+                r.failed = True
         finally:
+            if bs is not None:
+                try:
+                    bs.destroy()
+                except Exception as ex:
+                    self.errors.append(repr(ex))
             with self.cv:
                 for r in wave:
                     self.used -= r.footprint
@@ -313,7 +322,7 @@ class ServingEngine:
 
 
 def summarize(done, wall):
-    lat = sorted(r.t_done - r.arrival for r in done if r.t_done >= 0)
+    lat = sorted(r.t_done - r.arrival for r in done if r.t_done >= 0 and not getattr(r, "failed", False))
 
     def pct(q):
         if not lat:
@@ -321,8 +330,9 @@ def summarize(done, wall):
         k = min(len(lat) - 1, max(0, int(round(q / 100.0 * (len(lat) - 1)))))
         return lat[k]
 
-    solves = sum(r.nrhs for r in done)
-    return dict(requests=len(done), solves=solves, wall_s=wall,
+    ok = [r for r in done if not getattr(r, "failed", False)]
+    solves = sum(r.nrhs for r in ok)
+    return dict(requests=len(done), failed=len(done) - len(ok), solves=solves, wall_s=wall,
                 solves_per_s=solves / wall if wall > 0 else 0.0,
                 requests_per_s=len(done) / wall if wall > 0 else 0.0,
                 p50_s=pct(50), p99_s=pct(99),

@@ -10,7 +10,8 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BT_FP64, BT_GRAPH, BT_MIXED, BT_PLAIN, BT_SIGMA_ANTIHERMITIAN, BTError, check, make_desc
+from ._lib import (BT_DIAG_ONLY, BT_FP64, BT_GRAPH, BT_MIXED, BT_PLAIN, BT_SIGMA_ANTIHERMITIAN, BTError,
+                   BTToleranceError, check, check_tol, make_desc)
 
 FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
 
@@ -125,15 +126,17 @@ class Solver:
     def selected_solve(self, B: DeviceBlocks, XL: DeviceBlocks):
         err, fb = C.c_double(), C.c_int()
         self._keep.extend([B, XL])
-        check(_lib.lib().bt_si_sq_selected_solve(self._h, self._blocks(B), self._blocks(XL),
-                                                 C.byref(err), C.byref(fb)), self._h)
+        st = _lib.lib().bt_si_sq_selected_solve(self._h, self._blocks(B), self._blocks(XL),
+                                                C.byref(err), C.byref(fb))
+        check_tol(st, self._h, err.value, bool(fb.value))
         return err.value, bool(fb.value)
 
     def solve(self, A: DeviceBlocks, B: DeviceBlocks, XR: DeviceBlocks, XL: DeviceBlocks):
         err, fb = C.c_double(), C.c_int()
         self._keep = [A, B, XR, XL]
-        check(_lib.lib().bt_si_sq_solve(self._h, self._blocks(A), self._blocks(B), self._blocks(XR),
-                                        self._blocks(XL), C.byref(err), C.byref(fb)), self._h)
+        st = _lib.lib().bt_si_sq_solve(self._h, self._blocks(A), self._blocks(B), self._blocks(XR),
+                                       self._blocks(XL), C.byref(err), C.byref(fb))
+        check_tol(st, self._h, err.value, bool(fb.value))
         return err.value, bool(fb.value)
 
     def sync(self):
@@ -200,8 +203,8 @@ class BatchSolver:
         self._keep = (A, B, XR, XL)
         err = (C.c_double * n)()
         fb = (C.c_int * n)()
-        check(_lib.lib().bt_si_sq_batch_solve(self._h, arr(A), arr(B), arr(XR), arr(XL), err, fb),
-              self._h)
+        st = _lib.lib().bt_si_sq_batch_solve(self._h, arr(A), arr(B), arr(XR), arr(XL), err, fb)
+        check_tol(st, self._h, list(err), [bool(x) for x in fb])
         return list(err), [bool(x) for x in fb]
 
     def selected_solve(self, B, XL):
@@ -213,7 +216,8 @@ class BatchSolver:
         self._keep2 = (B, XL)
         err = (C.c_double * n)()
         fb = (C.c_int * n)()
-        check(_lib.lib().bt_si_sq_batch_selected_solve(self._h, barr, larr, err, fb), self._h)
+        st = _lib.lib().bt_si_sq_batch_selected_solve(self._h, barr, larr, err, fb)
+        check_tol(st, self._h, list(err), [bool(x) for x in fb])
         return list(err), [bool(x) for x in fb]
 
     def sync(self):
@@ -242,7 +246,8 @@ def batch_workspace_bytes(specs) -> int:
 
 
 __all__ = ["DeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
-           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN", "BTError",
+           "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN",
+           "BT_DIAG_ONLY", "BTError", "BTToleranceError",
            "autotune", "tune_table", "set_tune_table"]
 
 
@@ -319,3 +324,4 @@ def diag_inverse(src, stream=None):
     if status not in (_lib.BT_OK, _lib.BT_ERR_SINGULAR):
         check(status)
     return dst, (bad.value if status == _lib.BT_ERR_SINGULAR else -1)
+

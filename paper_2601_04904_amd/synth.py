@@ -34,7 +34,7 @@ import numpy as np
 
 __all__ = [
     "BTA", "gen_A", "gen_B", "gen_problem", "CONFIGS", "config_problem",
-    "batch_specs", "serving_trace", "equilibrium_B",
+    "batch_specs", "serving_trace", "equilibrium_B", "perturb",
 ]
 
 
@@ -162,6 +162,22 @@ def equilibrium_B(A: BTA, c: complex = 1.0) -> BTA:
             B.arrow_bottom[i] = c * (A.arrow_right[i].conj().T - A.arrow_bottom[i])
         B.tip[:] = c * (A.tip.conj().T - A.tip)
     return B
+
+
+def perturb(M: BTA, rel: float, seed: int) -> BTA:
+    """Copy of M with every entry x replaced by x (1 + rel u), u uniform in the
+    complex square [-1, 1] + i[-1, 1] (seeded).  With rel near the unit
+    roundoff, solving the copy with the same algorithm gives a second result
+    whose rounding errors are independent of the first: the spread of the two
+    measures how much that algorithm and input amplify rounding.  Pure input
+    construction."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = M.copy()
+    for f in out.fields():
+        if f.size:
+            u = rng.uniform(-1.0, 1.0, f.shape) + 1j * rng.uniform(-1.0, 1.0, f.shape)
+            f *= 1.0 + rel * u
+    return out
 
 
 @dataclass

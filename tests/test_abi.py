@@ -76,6 +76,15 @@ def test_invalid_descriptors(n, b, a, P, bounds):
     assert len(_lib.lib().bt_si_sq_last_error(None)) > 0
 
 
+@pytest.mark.parametrize("n,b,a,P", [(40, 8, 12, 17), (48, 6, 10, 24), (80, 4, 3, 40)])
+def test_many_partitions_with_arrow_plan(n, b, a, P):
+    """More than 16 partitions with an arrow tip: the tip sum has P + 1 inputs,
+    more than one block-sum operation takes, so it is chained; the plan
+    compiles (a sum with too many inputs would make the dry run fail)."""
+    d = make_desc(n, b, a, P)
+    assert _lib.lib().bt_si_sq_workspace_bytes(C.byref(d)) > 0, _lib.lib().bt_si_sq_last_error(None)
+
+
 def _flops(n, b, a, P, bounds=None):
     d = make_desc(n, b, a, P, bounds)
     ex, us = C.c_double(), C.c_double()
@@ -216,3 +225,4 @@ def test_diag_gemm_rejects_operands_past_32bit_offsets(opA, opB, big):
                               zero, None, 64, dummy, 64, 0, -1, None)
     assert st == BT_ERR_INVALID
     assert b"2 GiB" in L.bt_si_sq_last_error(None)
+

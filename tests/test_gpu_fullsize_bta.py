@@ -6,9 +6,12 @@ The same two checks as the BT full-size test: the block-row identities
 sum_j A_ij X^R_ji = I and sum_j A_ij X^<_ji = sum_j B_ij (X^R_ij)^H on every
 block row, the arrow tip row included (j over i-1, i, i+1 and the tip; every
 block for the tip row), held to 4x the residual the oracle's own 16-partition
-sweep leaves; and the element-wise comparison with the oracle's sequential
-BTA sweep, held to 4x the spread between the oracle's two orderings.  Both
-references are stored in tests/golden/fullsize_bta_spread.json.
+sweep leaves; and the element-wise comparison with the oracle's result of the
+same form (oracle.prgf, same bounds, reduced system split in two), held to
+max(1e-11, 4 x that form's FP64 floor: the spread between two oracle
+evaluations whose rounding differs).  Both references are stored in
+tests/golden/fullsize_floors_bta_n128_b384_a512.json, written by
+tests/golden/make_fullsize_floors.py from the oracle alone.
 """
 import json
 import os
@@ -59,11 +62,11 @@ def residuals_bta(A, B, XR, XL):
     return wr, wl
 
 
-def spread():
-    with open(os.path.join(HERE, "golden", "fullsize_bta_spread.json")) as f:
+def floors():
+    with open(os.path.join(HERE, "golden", "fullsize_floors_bta_n128_b384_a512.json")) as f:
         rec = json.load(f)
     assert rec["workload"] == "bta_n128_b384_a512"
-    return rec
+    return rec["forms"]
 
 
 @pytest.fixture(scope="module")
@@ -81,7 +84,7 @@ def result(S):
     print(f"[fullsize-bta] GPU solve n={n} b={b} a={a} partitions=16", flush=True)
     dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
     XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
-    sol = S.Solver(n, b, a, partitions=16)
+    sol = S.Solver(n, b, a, partitions=16, bounds=DEFAULT_BOUNDS_P16)
     sol.solve(dA, dB, XR, XL)
     sol.sync()
     out = (A, B, XR.to_host(), XL.to_host())
@@ -96,20 +99,21 @@ def test_fullsize_bta_default_bounds(S):
 def test_fullsize_bta_identities(result):
     A, B, XR, XL = result
     wr, wl = residuals_bta(A, B, XR, XL)
-    ref = spread()["partitioned_residuals"]
+    ref = floors()["P16"]["residuals"]
     base = 16 * EPS * A.tip.shape[0]
     br, bl = max(base, 4 * ref["XR"]), max(base, 4 * ref["XL"])
     print(f"[fullsize-bta] residuals X^R {wr:.2e} X^< {wl:.2e} (bounds {br:.2e} / {bl:.2e})", flush=True)
     assert wr < br and wl < bl, (wr, wl)
 
 
-def test_fullsize_bta_against_oracle(result):
+def test_fullsize_bta_against_oracle_same_form(result):
     A, B, XR, XL = result
-    sp = spread()
-    print("[fullsize-bta] oracle sequential sweep", flush=True)
-    XRo, XLo = oracle.rgf_bta(A, B)
+    fl = floors()["P16"]["floor"]
+    print("[fullsize-bta] oracle, same form as the GPU: P=16", flush=True)
+    XRo, XLo = oracle.prgf(A, B, DEFAULT_BOUNDS_P16, reduced_split=True)
     eR, eL = rel_err(XR, XRo), rel_err(XL, XLo)
-    print(f"[fullsize-bta] vs oracle: X^R {eR:.2e} X^< {eL:.2e} "
-          f"(oracle spread {sp['XR_spread']:.2e} / {sp['XL_spread']:.2e})", flush=True)
-    assert eR <= max(1e-11, 4 * sp["XR_spread"]), eR
-    assert eL <= max(1e-11, 4 * sp["XL_spread"]), eL
+    bR, bL = max(1e-11, 4 * fl["XR"]), max(1e-11, 4 * fl["XL"])
+    print(f"[fullsize-bta] vs oracle (same form): X^R {eR:.2e} X^< {eL:.2e} "
+          f"(floor {fl['XR']:.2e} / {fl['XL']:.2e}, bounds {bR:.2e} / {bL:.2e})", flush=True)
+    assert eR <= bR, eR
+    assert eL <= bL, eL

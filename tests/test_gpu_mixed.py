@@ -53,11 +53,47 @@ def test_mixed_within_tolerance_or_fallback(S, n, b, a, P, eta):
 
 
 def test_forced_fallback_gives_fp64_accuracy(S):
+    """tol below what FP64 reaches: the re-run happens, its results are written
+    and FP64-accurate, and the call reports that the estimate is still above tol."""
     A, B = gen_problem(10, 40, 16, eta=1e-2, seed=3)
     R0, L0 = oracle.solve_dense(A, B)
-    XR, XL, est, fb = run(S, A, B, 2, tol=1e-15)
+    n, b, a = 10, 40, 16
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    sol = S.Solver(n, b, a, partitions=2, precision=S.BT_MIXED, tol=1e-15)
+    with pytest.raises(S.BTToleranceError) as ex:
+        sol.solve(dA, dB, XR, XL)
+    sol.sync()
+    assert ex.value.fallback and ex.value.err > 1e-15
+    assert rel_err(XR.to_host(), R0) < 1e-11 and rel_err(XL.to_host(), L0) < 1e-11
+    sol.destroy()
+
+
+def test_split_mixed_fallback_refactors(S):
+    """factor() then selected_solve() on a mixed handle: the FP64 re-run that
+    the estimate triggers repeats the factor too, so X^R and X^< both reach
+    FP64 accuracy even though the factor's A-chain ran with FP32 products."""
+    n, b, a = 12, 48, 0
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-2, seed=21)
+    R0, L0 = oracle.solve_dense(A, B)
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    sol = S.Solver(n, b, a, partitions=1, precision=S.BT_MIXED, tol=1e-9)
+    sol.factor(dA, XR)
+    sol.sync()
+    eR_mixed = rel_err(XR.to_host(), R0)
+    try:
+        est, fb = sol.selected_solve(dB, XL)
+    except S.BTToleranceError as ex:     # estimate still above 1e-9 after FP64: results written
+        est, fb = ex.err, ex.fallback
+    sol.sync()
+    eR, eL = rel_err(XR.to_host(), R0), rel_err(XL.to_host(), L0)
+    print(f"mixed factor X^R err {eR_mixed:.2e}; after selected_solve est={est:.2e} fb={fb} "
+          f"X^R {eR:.2e} X^< {eL:.2e}", flush=True)
+    assert eR_mixed > 1e-9          # the mixed factor alone is FP32-accurate
     assert fb
-    assert rel_err(XR, R0) < 1e-11 and rel_err(XL, L0) < 1e-11
+    assert eR < 1e-11 and eL < 1e-11
+    sol.destroy()
 
 
 def test_mixed_is_less_accurate_than_fp64_but_close(S):

@@ -59,6 +59,9 @@ CASES = [
     (18, 9, 5, 9, [0, 1, 3, 5, 7, 9, 11, 13, 15, 18]),
     (30, 12, 20, 12, None),
     (40, 8, 12, 16, None),
+    # more than 16 partitions with an arrow: the tip sum of P + 1 inputs is chained
+    (40, 8, 12, 17, None),
+    (48, 6, 10, 24, None),
 ]
 
 
@@ -70,6 +73,44 @@ def test_parity_small(S, n, b, a, P, bounds):
     XR, XL = run_solver(S, A, B, P, bounds)
     eR, eL = rel_err(XR, R0), rel_err(XL, L0)
     print(f"  err R={eR:.3e} L={eL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL
+
+
+def run_flags(S, A, B, partitions, flags):
+    n, b, a = A.diag.shape[0], A.diag.shape[1], A.tip.shape[0]
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    sol = S.Solver(n, b, a, partitions=partitions, flags=flags)
+    sol.solve(dA, dB, XR, XL)
+    sol.sync()
+    out = XR.to_host(), XL.to_host()
+    sol.destroy()
+    return out
+
+
+@pytest.mark.parametrize("n,b,a,P", [(12, 40, 0, 1), (14, 33, 0, 3), (9, 36, 20, 1), (10, 28, 24, 2)])
+def test_plain_schedule_parity(S, n, b, a, P):
+    """BT_PLAIN, the one-launch-per-product reference schedule behind every
+    "vs plain RGF" figure, against the oracle."""
+    print(f"case BT_PLAIN n={n} b={b} a={a} P={P}", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-3, seed=40 + n + b + a + P)
+    R0, L0 = oracle.solve_dense(A, B)
+    XR, XL = run_flags(S, A, B, P, S.BT_PLAIN)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    print(f"  err R={eR:.3e} L={eL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_config_bt_n16_b32_seed0(S, P):
+    """The small configuration as specified (n=16, b=32, E=0.3, eta=1e-3,
+    seed 0), sequential RGF and two partitions, every selected block."""
+    from paper_2601_04904_amd.synth import config_problem
+    A, B = config_problem("bt_n16_b32")
+    R0, L0 = oracle.solve_dense(A, B)
+    XR, XL = run_flags(S, A, B, P, 0)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    print(f"bt_n16_b32 P={P}: err R={eR:.3e} L={eL:.3e}", flush=True)
     assert eR < TOL and eL < TOL
 
 
