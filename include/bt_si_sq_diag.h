@@ -34,6 +34,26 @@ bt_status bt_si_sq_diag_gemm(int32_t m, int32_t n, int32_t k,
 bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t count,
                                 int32_t* bad_index, void* hip_stream);
 
+/* bt_si_sq_diag_inverse for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops that forbid hipMalloc): the same
+ * result from the same kernels, but every piece of scratch - job descriptors,
+ * the device status word, working copies, panel transforms, pivot arrays -
+ * lives in one fixed device array of the library (64 MiB on every device the
+ * library runs on, held until the process ends; its size is returned by
+ * bt_si_sq_diag_inverse_noalloc_max_bytes).  No hipMalloc, hipFree or other
+ * allocating call is made.  One call needs 256 + align256(64 count) + count *
+ * (align256(16 d^2) + align256(512 d) + 2 align256(4 d)) bytes; a larger
+ * request returns BT_ERR_INVALID before touching the device (message in
+ * bt_si_sq_last_error(NULL)).  All calls on one device share the array:
+ * calls that overlap on one device (other threads, other streams) race and
+ * must be serialised by the caller.  Waits for the stream, like
+ * bt_si_sq_diag_inverse. */
+bt_status bt_si_sq_diag_inverse_noalloc(const void* src, void* dst, int32_t d, int32_t count,
+                                        int32_t* bad_index, void* hip_stream);
+
+/* Size in bytes of the fixed scratch array of bt_si_sq_diag_inverse_noalloc. */
+size_t bt_si_sq_diag_inverse_noalloc_max_bytes(void);
+
 /* Schedule of a fused solve for this descriptor, as text: one line per
  * dependency level with its number of products, product tiles (64 x 32
  * complex) and inverses.  Pure host computation.  Writes at most cap bytes

@@ -27,6 +27,7 @@ EXPORTED = [
     "bt_si_sq_batch_count", "bt_si_sq_batch_selected_solve",
     "bt_si_sq_autotune", "bt_si_sq_tune_table",
     "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse", "bt_si_sq_diag_schedule",
+    "bt_si_sq_diag_inverse_noalloc", "bt_si_sq_diag_inverse_noalloc_max_bytes",
 ]
 
 KERNEL_NAMES = {0: "product_fp64", 1: "product_mixed", 2: "inv_panel", 3: "inv_init",
@@ -134,6 +135,11 @@ def lib():
     L.bt_si_sq_diag_inverse.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_int32), C.c_void_p]
     L.bt_si_sq_diag_inverse.restype = C.c_int
+    L.bt_si_sq_diag_inverse_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                                C.POINTER(C.c_int32), C.c_void_p]
+    L.bt_si_sq_diag_inverse_noalloc.restype = C.c_int
+    L.bt_si_sq_diag_inverse_noalloc_max_bytes.argtypes = []
+    L.bt_si_sq_diag_inverse_noalloc_max_bytes.restype = C.c_size_t
     L.bt_si_sq_diag_schedule.argtypes = [C.POINTER(bt_desc), C.c_char_p, C.c_size_t]
     L.bt_si_sq_diag_schedule.restype = C.c_size_t
     _lib = L

@@ -65,6 +65,30 @@ struct InvJob {
 constexpr int kInvNB = 16;          // panel width (panel rows live in registers)
 constexpr int kInvMaxDim = 1024;    // 512 threads x 2 rows at most
 
+// Scratch of one inverse job: W (d x d), Mm (2 x d x NB), perm and used (d
+// each), each piece starting on a 256-byte boundary.  inv_scratch_bytes is the
+// span of one job's pieces from a 256-aligned start, rounded up to 256.
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline size_t inv_scratch_bytes(int d) {
+    return align256((size_t)d * d * sizeof(double2)) + align256(2 * (size_t)d * kInvNB * sizeof(double2)) +
+           2 * align256((size_t)d * sizeof(int32_t));
+}
+
+// Points the job's scratch at pool + off (off 256-aligned); returns the end offset.
+__host__ __device__ inline size_t inv_bind_scratch(InvJob& j, char* pool, size_t off, int d) {
+    off = align256(off);
+    j.W = reinterpret_cast<double2*>(pool + off);
+    off += align256((size_t)d * d * sizeof(double2));
+    j.Mm = reinterpret_cast<double2*>(pool + off);
+    off += align256(2 * (size_t)d * kInvNB * sizeof(double2));
+    j.perm = reinterpret_cast<int32_t*>(pool + off);
+    off += align256((size_t)d * sizeof(int32_t));
+    j.used = reinterpret_cast<int32_t*>(pool + off);
+    off += align256((size_t)d * sizeof(int32_t));
+    return off;
+}
+
 // D = sum_j c_j op_j(X_j), op_j = X or X^H (elementwise, rows x cols, contiguous).
 constexpr int kMaxAdd = 17;
 struct AddOp {

@@ -453,6 +453,8 @@ __global__ void inv_finish(const InvJob* __restrict__ jobs) {
     }
 }
 
+hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
+
 hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     int chunks = (int)(((size_t)maxd * maxd + 255) / 256);
@@ -474,6 +476,18 @@ hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int pan
         default: hipLaunchKernelGGL((inv_step<512, 2>), dim3(njobs * wg), dim3(512), 0, s, d_jobs, panel, wg, status); break;
     }
     return hipGetLastError();
+}
+
+// The whole inverse of njobs matrices that all use the panel kernel shape of
+// dimension maxd: working copy, every panel launch, unscramble.
+hipError_t launch_inverse_sequence(const InvJob* d_jobs, int njobs, int maxd, DevStatus* status,
+                                   hipStream_t s) {
+    hipError_t e = launch_inv_init(d_jobs, njobs, maxd, s);
+    const int npanels = (maxd + kInvNB - 1) / kInvNB;
+    for (int p = 0; p <= npanels && e == hipSuccess; ++p)
+        e = launch_inv_step(d_jobs, njobs, inv_variant(maxd), p, maxd, status, s);
+    if (e == hipSuccess) e = launch_inv_finish(d_jobs, njobs, maxd, s);
+    return e;
 }
 
 hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s) {

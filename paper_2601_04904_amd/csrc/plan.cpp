@@ -56,11 +56,18 @@ hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_
 hipError_t launch_norms(const NormJob* d_jobs, int njobs, hipStream_t s);
 }  // namespace btsq
 
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+namespace btsq {
+// error message of a call that has no handle (bt_si_sq_last_error(NULL))
+void set_global_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace btsq
+
 using namespace btsq;
 
 namespace {
-
-thread_local std::string g_last_error;
 
 double2 cplx(double re, double im = 0.0) { return make_double2(re, im); }
 
@@ -896,7 +903,6 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
     pg.levels = nlevels;
     std::vector<std::vector<int>> bylevel(nlevels);
     for (int i = 0; i < (int)ops.size(); ++i) bylevel[ops[i].level].push_back(i);
-    const size_t NB = kInvNB;
     auto mk = [&](int type, size_t off, int count, int tiles, int mixed, int maxd, int panel,
                   size_t maxe, int cls, int level, int wait) {
         Launch L{type, off, count, tiles, mixed, maxd, panel, maxe};
@@ -929,11 +935,7 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                     j.dst = o.D.p;
                     j.d = d;
                     j.tag = o.tag;
-                    auto take = [&](size_t bytes) { poff = (poff + 255) & ~(size_t)255; char* p = inv_pool + poff; poff += bytes; return p; };
-                    j.W = reinterpret_cast<double2*>(take((size_t)d * d * sizeof(double2)));
-                    j.Mm = reinterpret_cast<double2*>(take(2 * (size_t)d * NB * sizeof(double2)));
-                    j.perm = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
-                    j.used = reinterpret_cast<int32_t*>(take((size_t)d * sizeof(int32_t)));
+                    poff = inv_bind_scratch(j, inv_pool, poff, d);
                     pg.inv.push_back(j);
                 }
                 pg.inv_scratch_bytes = std::max(pg.inv_scratch_bytes, poff + 256);

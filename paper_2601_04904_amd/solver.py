@@ -325,3 +325,19 @@ def diag_inverse(src, stream=None):
         check(status)
     return dst, (bad.value if status == _lib.BT_ERR_SINGULAR else -1)
 
+
+def diag_inverse_noalloc(src, dst=None, stream=None):
+    """bt_si_sq_diag_inverse_noalloc: the batched inverse with the library's fixed
+    scratch array (no device allocation by the library).  dst may be given
+    (preallocated) so that the call allocates nothing at all."""
+    torch = _torch()
+    assert src.is_contiguous()
+    if dst is None:
+        dst = torch.empty_like(src)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    bad = C.c_int32(-1)
+    status = _lib.lib().bt_si_sq_diag_inverse_noalloc(src.data_ptr(), dst.data_ptr(), src.shape[-1],
+                                                      src.shape[0], C.byref(bad), C.c_void_p(st.cuda_stream))
+    if status not in (_lib.BT_OK, _lib.BT_ERR_SINGULAR):
+        check(status)
+    return dst, (bad.value if status == _lib.BT_ERR_SINGULAR else -1)

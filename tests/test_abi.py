@@ -226,3 +226,18 @@ def test_diag_gemm_rejects_operands_past_32bit_offsets(opA, opB, big):
     assert st == BT_ERR_INVALID
     assert b"2 GiB" in L.bt_si_sq_last_error(None)
 
+
+def test_noalloc_inverse_rejects_requests_beyond_its_scratch():
+    """The allocation-free inverse checks its fixed scratch size on the host,
+    before any device call: too many or too large matrices are refused."""
+    L = _lib.lib()
+    cap = L.bt_si_sq_diag_inverse_noalloc_max_bytes()
+    assert cap == 64 << 20
+    fake = C.c_void_p(1 << 40)           # never dereferenced: the call returns first
+    bad = C.c_int32(0)
+    # 1024 x 1024 complex: 16 MiB each, four do not fit with their other scratch
+    assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 1024, 4, C.byref(bad), None) == BT_ERR_INVALID
+    assert b"scratch" in L.bt_si_sq_last_error(None)
+    assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 1025, 1, C.byref(bad), None) == BT_ERR_INVALID
+    assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 64, -1, C.byref(bad), None) == BT_ERR_INVALID
+    assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 64, 0, C.byref(bad), None) == BT_OK
