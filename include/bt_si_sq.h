@@ -80,7 +80,15 @@ typedef enum {
 } bt_precision;
 
 /* flags */
-#define BT_DIAG_ONLY 0x1u   /* reserved: drop the off-diagonal outputs (not yet honoured) */
+#define BT_DIAG_ONLY 0x1u   /* outputs are the diagonal blocks X_{i,i} (and X_{t,t}) only, the
+                               form Sec. II-B gives after Alg. 2: the off-diagonal blocks of
+                               X^R and X^< are computed only where a later backward step
+                               reads them again, into the workspace, and the others not at
+                               all (for sequential BT two of the 23 block products per step).
+                               The off-diagonal and arrow pointers of XR and XL are ignored
+                               and may be NULL.  Needs BT_FP64 (BT_ERR_INVALID with
+                               BT_MIXED, whose error estimate reads the off-diagonal
+                               blocks). */
 #define BT_PLAIN 0x2u       /* reference schedule: one launch per single-term block product
                                and per inverse, in program order, on one stream (no
                                grouping, no multi-term fusion, no stream overlap) */
@@ -236,9 +244,10 @@ int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h);
 typedef enum {
     BT_KERNEL_PRODUCT_FP64 = 0,   /* grouped complex products, FP64 MFMA */
     BT_KERNEL_PRODUCT_MIXED = 1,  /* grouped complex products, FP32 MFMA */
-    BT_KERNEL_INV_PANEL = 2,      /* inverse: panel elimination */
-    BT_KERNEL_INV_INIT = 3,       /* inverse: working copy */
-    BT_KERNEL_INV_FINISH = 4,     /* inverse: unscramble into the result */
+    BT_KERNEL_INV_PANEL = 2,      /* inverse: panel elimination (the launches also read the
+                                     block to invert and write the result) */
+    BT_KERNEL_INV_INIT = 3,       /* unused (kept for numbering) */
+    BT_KERNEL_INV_FINISH = 4,     /* unused (kept for numbering) */
     BT_KERNEL_SUM = 5,            /* elementwise block sums */
     BT_KERNEL_NORM = 6,           /* block norms of the residual check */
     BT_KERNEL_COUNT = 7

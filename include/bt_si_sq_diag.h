@@ -41,8 +41,8 @@ bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t c
  * lives in one fixed device array of the library (64 MiB on every device the
  * library runs on, held until the process ends; its size is returned by
  * bt_si_sq_diag_inverse_noalloc_max_bytes).  No hipMalloc, hipFree or other
- * allocating call is made.  One call needs 256 + align256(64 count) + count *
- * (align256(16 d^2) + align256(512 d) + 2 align256(4 d)) bytes; a larger
+ * allocating call is made.  One call needs 256 + align256(48 count) + count *
+ * (align256(16 d^2) + 2 align256(4 d)) bytes; a larger
  * request returns BT_ERR_INVALID before touching the device (message in
  * bt_si_sq_last_error(NULL)).  All calls on one device share the array:
  * calls that overlap on one device (other threads, other streams) race and

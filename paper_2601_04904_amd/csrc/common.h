@@ -54,8 +54,7 @@ __device__ inline int xcd_remap(int b, int g) {
 struct InvJob {
     const double2* src;
     double2* dst;
-    double2* W;       // d x d working copy, column-major
-    double2* Mm;      // 2 x (d x kInvNB) column-major: panel transform minus pivot columns, by panel parity
+    double2* W;       // d x d working matrix, column-major
     int32_t* perm;    // d pivot rows (perm[j] = pivot row of column j)
     int32_t* used;    // d flags
     int32_t d;
@@ -65,14 +64,13 @@ struct InvJob {
 constexpr int kInvNB = 16;          // panel width (panel rows live in registers)
 constexpr int kInvMaxDim = 1024;    // 512 threads x 2 rows at most
 
-// Scratch of one inverse job: W (d x d), Mm (2 x d x NB), perm and used (d
-// each), each piece starting on a 256-byte boundary.  inv_scratch_bytes is the
-// span of one job's pieces from a 256-aligned start, rounded up to 256.
+// Scratch of one inverse job: W (d x d), perm and used (d each), each piece
+// starting on a 256-byte boundary.  inv_scratch_bytes is the span of one job's
+// pieces from a 256-aligned start, rounded up to 256.
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 __host__ __device__ inline size_t inv_scratch_bytes(int d) {
-    return align256((size_t)d * d * sizeof(double2)) + align256(2 * (size_t)d * kInvNB * sizeof(double2)) +
-           2 * align256((size_t)d * sizeof(int32_t));
+    return align256((size_t)d * d * sizeof(double2)) + 2 * align256((size_t)d * sizeof(int32_t));
 }
 
 // Points the job's scratch at pool + off (off 256-aligned); returns the end offset.
@@ -80,8 +78,6 @@ __host__ __device__ inline size_t inv_bind_scratch(InvJob& j, char* pool, size_t
     off = align256(off);
     j.W = reinterpret_cast<double2*>(pool + off);
     off += align256((size_t)d * d * sizeof(double2));
-    j.Mm = reinterpret_cast<double2*>(pool + off);
-    off += align256(2 * (size_t)d * kInvNB * sizeof(double2));
     j.perm = reinterpret_cast<int32_t*>(pool + off);
     off += align256((size_t)d * sizeof(int32_t));
     j.used = reinterpret_cast<int32_t*>(pool + off);

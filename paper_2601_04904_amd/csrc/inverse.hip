@@ -2,27 +2,37 @@
 // inverse-instead-of-trsm formulation of Sec. II-B), by blocked Gauss-Jordan
 // elimination with partial pivoting inside the block.
 //
+// The elimination runs on M = A^T: a row-major d x d block read as a
+// column-major matrix is its transpose, so the caller's block is the working
+// matrix's starting value without a copy, and A^-1 = (M^-1)^T.
+//
 // Pivoting is implicit: no rows are swapped.  For column j the pivot is the
-// not-yet-used row of largest |re| + |im| (lowest row index on ties); that row
-// is scaled and column j is eliminated from every other row.  In place, the
-// slot of column j then holds column p_j of the accumulated transform M
-// (M A = Q, Q the permutation with Q e_j = e_{p_j}), so at the end
-//     A^-1[j][c] = W[p_j][pinv(c)].
+// not-yet-used row of M of largest |re| + |im| (lowest row index among
+// magnitudes equal to 11 mantissa bits); that row is scaled and column j is
+// eliminated from every other row.  In place, the slot of column j then
+// holds column p_j of the accumulated transform T (T M = Q, Q the
+// permutation with Q e_j = e_{p_j}), so at the end, with W the working matrix,
+//     M^-1[j][c] = W[p_j][pinv(c)],   A^-1[c][j] = W[p_j][pinv(c)].
 //
-// Layout: the working matrix W (d x d) and the panel transforms Mm (d x NB)
-// are stored column-major, element (r, c) at c * d + r.  Every kernel below
-// gives each lane its own rows, so a load or store of one column by a wave
-// covers 64 consecutive rows (1 KB) instead of 64 scattered pieces.
+// Layout: W (d x d) is column-major, element (r, c) at c * d + r.  Every
+// kernel below gives each lane its own rows, so a load or store of one column
+// by a wave covers 64 consecutive rows (1 KB) instead of 64 scattered pieces.
 //
-// Blocking: a panel of kInvNB columns is eliminated by one workgroup that
-// holds the panel rows in registers (one barrier per column: the best
-// candidate of every wave publishes its row and the reciprocal of its pivot
-// entry, every thread then picks the winner and updates its rows).  The
-// effect of the panel on the other columns is M_J = I + Mm Y, where
-//     Mm[:, s] = (panel column s) - e_{p_s}   (d x NB)
+// Blocking: panel p (kInvNB columns) is eliminated by one workgroup that
+// holds the panel rows in registers.  The effect of the panel on the other
+// columns is T_p = I + Tm Y with
+//     Tm[:, s] = (panel column s) - e_{p_s}     (d x NB, read from W)
 //     Y[s, :]  = W[p_s, :] outside the panel, 0 inside (NB x d),
-// applied in the next panel's launch as W += Mm Y: by the panel workgroup to
+// applied in the next panel's launch as W += Tm Y: by the panel workgroup to
 // its own block (look-ahead) and by the other workgroups to the rest.
+//
+// One launch per panel p = 0 .. np (np = ceil(d / NB)):
+//   p < np : the panel workgroup applies T_{p-1} to block p and eliminates it;
+//            every other column block except p - 1 takes T_{p-1}.
+//   p = np : every column block except np - 1 takes T_{np-1}, and all of them
+//            are written to the result, transposed and unscrambled.
+// Column blocks are read from the caller's block until they are first
+// written (block 0 and 1 by the panel workgroup, the others in launch 1).
 #include "common.h"
 #include <cfloat>
 #include <climits>
@@ -56,15 +66,20 @@ __device__ inline void cfms(double2& acc, double2 a, double2 b) {
     acc.y = fma(-a.y, b.x, acc.y);
 }
 
-// 1 / v = conj(v) / |v|^2, with v first scaled by a power of two so that
-// |v|^2 neither overflows nor underflows (one division).  A zero, infinite
-// or NaN v gives a non-finite or zero result, which the caller flags.
+// 1 / v = conj(v) / |v|^2.  v is first scaled by a power of two so that its
+// larger component lies in [0.5, 1), which puts |v|^2 in [0.25, 2); the
+// reciprocal of |v|^2 is the hardware estimate refined by two Newton steps
+// r <- r (2 - s r) (each at least doubles the number of correct bits).  A
+// zero, infinite or NaN v gives a NaN result, which the caller flags.
 __device__ inline double2 crecip(double2 v) {
     int e;
     (void)frexp(fmax(fabs(v.x), fabs(v.y)), &e);
     const double a = ldexp(v.x, -e), b = ldexp(v.y, -e);
-    const double inv = 1.0 / (a * a + b * b);
-    return make_double2(ldexp(a * inv, -e), ldexp(-b * inv, -e));
+    const double s = fma(a, a, b * b);
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(r, fma(-s, r, 1.0), r);
+    r = fma(r, fma(-s, r, 1.0), r);
+    return make_double2(ldexp(a * r, -e), ldexp(-b * r, -e));
 }
 
 // Maximum of a 32-bit value over the 64 lanes of a wave: DPP steps within
@@ -87,116 +102,120 @@ __device__ inline unsigned wave_umax(unsigned x) {
     return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Maximum of a 64-bit key over the wave: the high words first, then the low
-// words of the lanes whose high word is that maximum.
-__device__ inline unsigned long long wave_max_key(unsigned long long k) {
-    const unsigned hi = (unsigned)(k >> 32);
-    const unsigned h = wave_umax(hi);
-    const unsigned l = wave_umax(hi == h ? (unsigned)k : 0u);
-    return ((unsigned long long)h << 32) | l;
-}
-
-// Pivot key: the bit pattern of |re| + |im| of the candidate (non-finite
-// values clamped to the largest finite double) with the 11 low mantissa bits
-// replaced by 2047 - row.  Non-negative doubles order like their bit
-// patterns, so the largest key is the largest magnitude (to 41 mantissa bits)
-// and, among magnitudes equal to that precision, the lowest row.  Every
-// candidate row is below 1024, so a candidate's key is at least 1024 and 0
-// means "no candidate".
-__device__ inline unsigned long long pivot_key(double2 v, int row) {
+// Pivot key (32 bits): bits 62..41 of the double |re| + |im| (its exponent
+// and the top 11 bits of its mantissa; non-finite values clamped to the
+// largest finite double) above 1023 - row in the low 10 bits.  Non-negative
+// doubles order like their bit patterns, so the largest key is the largest
+// magnitude to 11 mantissa bits (any candidate within a relative 2^-11 of the
+// largest is as good a pivot) and, among those, the lowest row.  Rows are
+// below 1024.  0 means "no candidate" (it is also the key of a zero entry in
+// row 1023; either way the column has no usable pivot).
+__device__ inline unsigned pivot_key(double2 v, int row) {
     double m = fabs(v.x) + fabs(v.y);
     if (!(m <= DBL_MAX)) m = DBL_MAX;
-    return ((unsigned long long)__double_as_longlong(m) & ~2047ull) | (unsigned long long)(2047 - row);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+    return ((unsigned)(bits >> 41) << 10) | (unsigned)(1023 - row);
 }
 
-__device__ inline int key_row(unsigned long long key) {
-    return 2047 - (int)(key & 2047ull);
+__device__ inline int key_row(unsigned key) { return 1023 - (int)(key & 1023u); }
+
+constexpr int kUpdCols = 8;    // columns per update workgroup (half a panel block)
+
+// Where column block `blk` of the working matrix lives at the start of launch
+// p: the caller's block (read as column-major M) until its first write.
+__device__ inline const double2* block_source(const InvJob& J, int blk, int p) {
+    const bool written = blk <= 1 ? p > blk : p > 1;
+    return written ? J.W : J.src;
 }
 
-// W = src transposed into the column-major working layout, through 16 x 16
-// LDS tiles so that both the row-major reads and the column-major writes are
-// contiguous across threads.  256 threads per workgroup.
-__global__ void inv_init(const InvJob* __restrict__ jobs) {
-    __shared__ double2 tile[16][17];
-    const InvJob J = jobs[blockIdx.y];
-    const int d = J.d;
-    const int nt = (d + 15) / 16;
-    const int tid = threadIdx.x;
-    const int a = tid >> 4, b = tid & 15;
-    for (int t = blockIdx.x; t < nt * nt; t += gridDim.x) {
-        const int ti = t / nt, tj = t - ti * nt;
-        const int r = ti * 16 + a, c = tj * 16 + b;
-        if (r < d && c < d) tile[a][b] = J.src[(size_t)r * d + c];
-        __syncthreads();
-        const int c2 = tj * 16 + a, r2 = ti * 16 + b;
-        if (r2 < d && c2 < d) J.W[(size_t)c2 * d + r2] = tile[b][a];
-        __syncthreads();
-    }
-    for (int e = blockIdx.x * blockDim.x + tid; e < d; e += gridDim.x * blockDim.x) J.used[e] = 0;
-}
-
-// One launch per panel p.  Per matrix, workgroup 0 (the panel workgroup)
-// applies the transform of panel p-1 to block p (look-ahead) and then
-// eliminates block p; workgroups 1.. apply the transform of panel p-1 to the
-// other 8-column blocks (all but blocks p-1 and p), each first gathering the
-// pivot rows of its own columns, so no workgroup reads what another writes.
-// Mm is double-buffered by panel parity (Mm + (p % 2) * d * NB).
-constexpr int kUpdCols = 8;
-
+// Update workgroup u of launch p: its 16 columns take T_{p-1}; in the last
+// launch they are also written to the result.  It gathers the pivot rows of
+// panel p-1 restricted to its own columns first, so no workgroup reads what
+// another writes in the same launch.
 template <int T, int R>
 __device__ void step_update(const InvJob& J, int p, int u, int tid) {
     constexpr int NB = kInvNB;
     constexpr int UC = kUpdCols;
     __shared__ double2 G[NB][UC];
+    __shared__ int prow[NB];
+    __shared__ int pinv[kInvMaxDim];
     const int d = J.d;
+    const int np = (d + NB - 1) / NB;
     const int c0 = u * UC;
-    if (c0 >= d || (p - 1) * NB >= d) return;   // no such columns / no panel p-1 for this matrix
     const int blk = c0 / NB;
-    if (blk == p - 1 || blk == p) return;
-    const int q0 = (p - 1) * NB;                  // first column of panel p-1
+    if (c0 >= d || p == 0 || p > np) return;          // no such columns / nothing to apply
+    const bool last = p == np;
+    if (blk == p) return;                              // the panel workgroup's block
+    const bool apply = blk != p - 1;                   // block p-1 is final after launch p-1
+    if (!apply && !last) return;                       // nothing to do until the write-out
+    const int q0 = (p - 1) * NB;                       // first column of panel p-1
     const int nc = min(NB, d - q0);
-    const double2* Mm = J.Mm + (size_t)((p - 1) & 1) * d * NB;
-    if (tid < NB * UC) {
-        const int s = tid / UC, j = tid % UC;
-        const int sr = min(s, nc - 1), cc = min(c0 + j, d - 1);
-        const double2 v = J.W[(size_t)cc * d + J.perm[q0 + sr]];
-        G[s][j] = (s < nc && c0 + j < d) ? v : make_double2(0.0, 0.0);
+    const int ncols = min(UC, d - c0);
+    const double2* src = block_source(J, blk, p);
+    if (tid < NB) prow[tid] = tid < nc ? J.perm[q0 + tid] : -1;
+    if (last) {
+        // inverse permutation (cleared first: after a singular pivot the
+        // pivot rows need not be a permutation, and every index stays in range)
+        for (int e = tid; e < d; e += T) pinv[e] = 0;
+        __syncthreads();
+        for (int e = tid; e < d; e += T) pinv[J.perm[e]] = e;
     }
     __syncthreads();
-    const int ncols = min(UC, d - c0);
+    if (apply && tid < NB * UC) {
+        const int s = tid / UC, j = tid % UC;
+        const int sr = min(s, nc - 1), cc = c0 + min(j, ncols - 1);
+        const double2 v = src[(size_t)cc * d + prow[sr]];
+        G[s][j] = (s < nc && j < ncols) ? v : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = tid + q * T;
         if (r >= d) continue;
         double2 acc[UC];
-        const double2* wcol = J.W + (size_t)c0 * d + r;
-        const double2* mcol = Mm + r;
+        const double2* wcol = src + (size_t)c0 * d + r;
 #pragma unroll
         for (int j = 0; j < UC; ++j) acc[j] = wcol[(size_t)min(j, ncols - 1) * d];
+        if (apply) {
+            const double2* mcol = J.W + (size_t)q0 * d + r;
 #pragma unroll 2
-        for (int s = 0; s < NB; s += 4) {
-            double2 m[4];
+            for (int s = 0; s < NB; s += 4) {
+                double2 m[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) m[i] = mcol[(size_t)(s + i) * d];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < UC; ++j) {
-                    cfma(acc[j], m[i], G[s + i][j]);
+                for (int i = 0; i < 4; ++i) {
+                    m[i] = s + i < nc ? mcol[(size_t)(s + i) * d] : make_double2(0.0, 0.0);
+                    if (prow[s + i] == r) m[i].x -= 1.0;
                 }
-        }
-        double2* wout = J.W + (size_t)c0 * d + r;
 #pragma unroll
-        for (int j = 0; j < UC; ++j)
-            if (j < ncols) wout[(size_t)j * d] = acc[j];
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < UC; ++j) cfma(acc[j], m[i], G[s + i][j]);
+            }
+        }
+        if (!last) {
+            double2* wout = J.W + (size_t)c0 * d + r;
+#pragma unroll
+            for (int j = 0; j < UC; ++j)
+                if (j < ncols) wout[(size_t)j * d] = acc[j];
+        } else {
+            // A^-1[perm[col]][pinv(r)] = W[r][col]
+            const int jr = pinv[r];
+#pragma unroll
+            for (int j = 0; j < UC; ++j)
+                if (j < ncols) J.dst[(size_t)J.perm[c0 + j] * d + jr] = acc[j];
+        }
     }
 }
 
+// Panel workgroup of launch p: applies T_{p-1} to block p (look-ahead) and
+// eliminates its columns.  The look-ahead is a run-time loop over the
+// transform columns (every register index in it is static); the column loop
+// is unrolled, since it indexes the panel registers by column.
 template <int T, int R>
 __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     constexpr int NB = kInvNB;
     constexpr int NW = T / 64;
-    __shared__ unsigned long long cand_key[2][NW];
+    __shared__ unsigned cand_key[2][NW];
     __shared__ double2 cand_ip[2][NW];
     __shared__ double2 cand_row[2][NW][NB];
     __shared__ int piv[NB];
@@ -206,36 +225,32 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     const int d = J.d;
     const int j0 = p * NB;
     if (j0 >= d) return;
-    // the panel is the critical path of the launch: its waves win instruction
-    // issue over the update workgroups and other kernels' waves on the CU
-    __builtin_amdgcn_s_setprio(3);
     const int nc = min(NB, d - j0);
     const int lane = tid & 63, wave = tid >> 6;
+    const double2* src = block_source(J, p, p);
 
-    // All global reads are issued here, before any wait: this workgroup's rows
-    // of block p, their used flags, their rows of the panel p-1 transform and
-    // the pivot rows of panel p-1.
+    // this workgroup's rows of block p and their used flags
     double2 P[R][NB];
     int used[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = min(tid + q * T, d - 1);
-        const double2* col = J.W + (size_t)j0 * d + r;
-        used[q] = J.used[r];
+        const double2* col = src + (size_t)j0 * d + r;
+        used[q] = p > 0 ? J.used[r] : 0;
 #pragma unroll
         for (int c = 0; c < NB; ++c) P[q][c] = col[(size_t)min(c, nc - 1) * d];
     }
     if (p > 0) {
         const int q0 = (p - 1) * NB;
         const int pnc = min(NB, d - q0);
-        constexpr int MG = R == 1 ? NB : 4;          // transform entries held at once
-        const double2* Mm = J.Mm + (size_t)((p - 1) & 1) * d * NB;
-        double2 m[R][MG];
+        const double2* Tm = J.W + (size_t)q0 * d;     // panel p-1 columns, final
+        // transform entries of columns 0 and 1, loaded two columns ahead below
+        double2 ma[R], mb[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const double2* mcol = Mm + min(tid + q * T, d - 1);
-#pragma unroll
-            for (int i = 0; i < MG; ++i) m[q][i] = mcol[(size_t)i * d];
+            const double2* mcol = Tm + min(tid + q * T, d - 1);
+            ma[q] = mcol[0];
+            mb[q] = mcol[(size_t)min(1, pnc - 1) * d];
         }
         if (tid < NB) prev[tid] = tid < pnc ? J.perm[q0 + tid] : -1;
         if (tid < NB && tid >= pnc) {
@@ -258,25 +273,30 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
             }
         }
         __syncthreads();
-        // look-ahead: block p += Mm_{p-1} G
+        // look-ahead: block p += Tm_{p-1} G, Tm = panel columns minus the
+        // unit entries at the pivot rows, one transform column per step
+        for (int s = 0; s < pnc; ++s) {
+            double2 mc[R];
 #pragma unroll
-        for (int s0 = 0; s0 < NB; s0 += MG) {
-            if (s0 > 0) {
+            for (int q = 0; q < R; ++q) {
+                const double2* mcol = Tm + min(tid + q * T, d - 1);
+                mc[q] = mcol[(size_t)min(s + 2, pnc - 1) * d];
+            }
+            const int pr = prev[s];
 #pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const double2* mcol = Mm + min(tid + q * T, d - 1);
+            for (int q = 0; q < R; ++q)
+                if (pr == tid + q * T) ma[q].x -= 1.0;
 #pragma unroll
-                    for (int i = 0; i < MG; ++i) m[q][i] = mcol[(size_t)(s0 + i) * d];
-                }
+            for (int c = 0; c < NB; ++c) {
+                const double2 g = G[s][c];
+#pragma unroll
+                for (int q = 0; q < R; ++q) cfma(P[q][c], ma[q], g);
             }
 #pragma unroll
-            for (int i = 0; i < MG; ++i)
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    const double2 g = G[s0 + i][c];
-#pragma unroll
-                    for (int q = 0; q < R; ++q) cfma(P[q][c], m[q][i], g);
-                }
+            for (int q = 0; q < R; ++q) {
+                ma[q] = mb[q];
+                mb[q] = mc[q];
+            }
         }
     }
 #pragma unroll
@@ -293,7 +313,7 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     // the reciprocal of its pivot entry and its whole row.  Written with
     // selects rather than branches, so that the search of a column and the
     // row updates around it form one block the compiler can interleave.
-    unsigned long long bk, wk;
+    unsigned bk, wk;
     double2 bip;
     int bq;
     auto search = [&](auto sc) {
@@ -303,15 +323,15 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
         double2 pv = P[0][s];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const unsigned long long kq = pivot_key(P[q][s], tid + q * T);
-            const unsigned long long k = used[q] ? 0ull : kq;
+            const unsigned kq = pivot_key(P[q][s], tid + q * T);
+            const unsigned k = used[q] ? 0u : kq;
             const bool take = k > bk;
             bk = take ? k : bk;
             bq = take ? q : bq;
             pv = sel2(take, P[q][s], pv);
         }
         bip = crecip(pv);
-        wk = wave_max_key(bk);
+        wk = wave_umax(bk);
     };
     auto publish = [&](int sb) {
         if (wk == 0) {
@@ -351,12 +371,9 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
         constexpr int sb = s & 1;
         if (s >= nc) return;
         __syncthreads();
-        unsigned long long gk = cand_key[sb][0];
+        unsigned gk = cand_key[sb][0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            const unsigned long long k = cand_key[sb][w];
-            gk = k > gk ? k : gk;
-        }
+        for (int w = 1; w < NW; ++w) gk = max(gk, cand_key[sb][w]);
         const int gr = gk == 0 ? -1 : key_row(gk);
         const int gw = gk == 0 ? 0 : min((gr % T) >> 6, NW - 1);
         // the winning row's reciprocal pivot and entries, read together
@@ -364,7 +381,7 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
         double2 v[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) v[c] = cand_row[sb][gw][c];
-        bad = bad || gk == 0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX) || (ip.x == 0.0 && ip.y == 0.0);
+        bad = bad || gk == 0 || !(fabs(ip.x) + fabs(ip.y) <= DBL_MAX);
         double2 g[R];
         bool pr[R];
 #pragma unroll
@@ -400,26 +417,15 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     if (bad && tid == 0 && atomicCAS(&status->code, 0, 3) == 0) status->tag = J.tag;
     __syncthreads();
 
-    // write back block p (rows scaled by sc) and Mm_p = block p minus the
-    // pivot unit entries
-    double2* Mm = J.Mm + (size_t)(p & 1) * d * NB;
+    // write back block p (rows scaled by sc), the used flags and the pivots
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = tid + q * T;
         if (r < d) {
             double2* col = J.W + (size_t)j0 * d + r;
-            double2* mcol = Mm + r;
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c < nc) {
-                    double2 v = cmul_i(sc[q], P[q][c]);
-                    col[(size_t)c * d] = v;
-                    if (piv[c] == r) v.x -= 1.0;
-                    mcol[(size_t)c * d] = v;
-                } else {
-                    mcol[(size_t)c * d] = make_double2(0.0, 0.0);
-                }
-            }
+            for (int c = 0; c < NB; ++c)
+                if (c < nc) col[(size_t)c * d] = cmul_i(sc[q], P[q][c]);
             J.used[r] = used[q];
         }
     }
@@ -434,34 +440,7 @@ void inv_step(const InvJob* __restrict__ jobs, int p, int wg_per_job, DevStatus*
     const int w = blockIdx.x - job * wg_per_job;
     const InvJob J = jobs[job];
     if (w == 0) step_panel<T, R>(J, p, threadIdx.x, status);
-    else if (p > 0) step_update<T, R>(J, p, w - 1, threadIdx.x);
-}
-
-__global__ void inv_finish(const InvJob* __restrict__ jobs) {
-    __shared__ int perm[kInvMaxDim];
-    __shared__ int pinv[kInvMaxDim];
-    const InvJob J = jobs[blockIdx.y];
-    const int d = J.d;
-    for (int e = threadIdx.x; e < d; e += blockDim.x) perm[e] = J.perm[e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < d; e += blockDim.x) pinv[perm[e]] = e;
-    __syncthreads();
-    for (int j = blockIdx.x; j < d; j += gridDim.x) {
-        const double2* src = J.W + perm[j];           // row perm[j] of the column-major W
-        double2* dst = J.dst + (size_t)j * d;
-        for (int c = threadIdx.x; c < d; c += blockDim.x) dst[c] = src[(size_t)pinv[c] * d];
-    }
-}
-
-hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
-
-hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
-    int chunks = (int)(((size_t)maxd * maxd + 255) / 256);
-    if (chunks > 64) chunks = 64;
-    if (chunks < 1) chunks = 1;
-    hipLaunchKernelGGL(inv_init, dim3(chunks, njobs), dim3(256), 0, s, d_jobs);
-    return hipGetLastError();
+    else step_update<T, R>(J, p, w - 1, threadIdx.x);
 }
 
 int inv_variant(int d) { return d <= 256 ? 0 : d <= 512 ? 1 : 2; }
@@ -479,23 +458,14 @@ hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int pan
 }
 
 // The whole inverse of njobs matrices that all use the panel kernel shape of
-// dimension maxd: working copy, every panel launch, unscramble.
+// dimension maxd: one launch per panel plus the final one.
 hipError_t launch_inverse_sequence(const InvJob* d_jobs, int njobs, int maxd, DevStatus* status,
                                    hipStream_t s) {
-    hipError_t e = launch_inv_init(d_jobs, njobs, maxd, s);
+    hipError_t e = hipSuccess;
     const int npanels = (maxd + kInvNB - 1) / kInvNB;
     for (int p = 0; p <= npanels && e == hipSuccess; ++p)
         e = launch_inv_step(d_jobs, njobs, inv_variant(maxd), p, maxd, status, s);
-    if (e == hipSuccess) e = launch_inv_finish(d_jobs, njobs, maxd, s);
     return e;
-}
-
-hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
-    int rows = maxd < 64 ? maxd : 64;
-    if (rows < 1) rows = 1;
-    hipLaunchKernelGGL(inv_finish, dim3(rows, njobs), dim3(256), 0, s, d_jobs);
-    return hipGetLastError();
 }
 
 }  // namespace btsq

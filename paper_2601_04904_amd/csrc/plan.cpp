@@ -34,6 +34,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_set>
 #include <memory>
 #include <string>
 #include <atomic>
@@ -47,8 +48,6 @@ int gemm_tiles_shape(int m, int n, int shape);
 int gemm_tiles_n_shape(int n, int shape);
 int gemm_shape_bm(int shape);
 int gemm_shape_bn(int shape);
-hipError_t launch_inv_init(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
-hipError_t launch_inv_finish(const InvJob* d_jobs, int njobs, int maxd, hipStream_t s);
 int inv_variant(int d);   // panel kernel shape for dimension d: 0 (256 x 1 rows), 1 (256 x 2), 2 (512 x 2)
 hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int panel, int maxd,
                            DevStatus* status, hipStream_t s);
@@ -234,6 +233,9 @@ struct Builder {
     bool check = false;   // emit the FP64 selected-residual check (mixed path)
     bool plain = false;   // reference schedule: single-term products, one stream
     bool antiH = false;   // B anti-Hermitian: derive one block of each conjugate pair
+    bool diag_only = false;   // outputs: diagonal blocks only (off-diagonal ones kept
+                              // only where the backward sweep reads them again)
+    std::unordered_set<uint64_t> needX;   // pairs (u, v) some backward step reads: N(k) x N(k)
     int instance = 0;     // instance id within a batch (reported with singular blocks)
     MatRef Ib, Ia;        // identity blocks (filled once at create)
     MatRef norm_out;      // norms written by the check (5 per block row)
@@ -297,7 +299,7 @@ struct Builder {
         if (it != store.end()) return it->second;
         MatRef m = alloc(D.dim(u), D.dim(v));     // reserved for every pair, used when the caller gives none
         const bt_blocks& out = lesser ? XLext : XRext;
-        if (selected(u, v)) {
+        if (selected(u, v) && !(diag_only && u != v)) {
             MatRef e = ext_block(out, lesser ? 3 : 2, u, v);
             const bool have = (u == D.n && v == D.n) ? out.tip != nullptr
                             : (v == D.n) ? out.arrow_right != nullptr
@@ -416,6 +418,8 @@ struct Builder {
         const bool mx = mixed_bulk && !reduced_stage;
         const int dk = D.dim(k);
         const double2 one = cplx(1), mone = cplx(-1), zero = cplx(0);
+        for (int u : N)
+            for (int v : N) needX.insert(key3(u, v, 0));
         r.S = alloc(dk, dk);
         cur_cls = 1;   // the A-chain: inverse, T and Schur updates
         inv(emitA(), cur(false, k, k, tip_tag(k, k, part_tag)), r.S, (instance << 16) | k);
@@ -497,7 +501,11 @@ struct Builder {
         }
         for (int u : N)
             gemm(emitA(), xloc(false, u, k), MatRef{}, zero, {{r.rho[u], false, r.S, false, mone}}, mx);
+        // X_kv: an output, or read again by a later backward step; with
+        // diagonal outputs only it is dropped where nothing reads it (the
+        // transient-only form after Alg. 2)
         for (int v : N) {
+            if (diag_only && !needX.count(key3(k, v, 0))) continue;
             std::vector<TermSpec> ts;
             for (int w : N) ts.push_back({r.tau[w], false, xloc(false, w, v), false, mone});
             gemm(emitA(), xloc(false, k, v), MatRef{}, zero, ts, mx);
@@ -541,6 +549,7 @@ struct Builder {
         // -(X^<_{k,u})^H couples the errors of the two recurrences and was
         // measured to amplify rounding by 10^2 - 10^3 on ill-conditioned inputs.
         for (int u : N) {
+            if (diag_only && !needX.count(key3(u, k, 0))) continue;   // as X_kv above
             std::vector<TermSpec> ts;
             for (int w : N) ts.push_back({xloc(true, u, w), false, r.tau[w], true, mone});
             gemm(emitB(), xloc(true, u, k), r.Y21[u], one, ts, mx);
@@ -767,7 +776,7 @@ int levelize(std::vector<OpRec>& ops, bool plain = false) {
 }
 
 struct Launch {
-    int type;         // 0 gemm, 1 inv_init, 3 inv_finish, 4 add, 5 norms, 6 inverse panel step
+    int type;         // 0 gemm, 4 add, 5 norms, 6 inverse panel step
     size_t off;       // element offset into the typed array
     int count;
     int tiles;        // gemm: total tiles
@@ -946,18 +955,23 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                     ++vcount[v];
                     vmaxd[v] = std::max(vmaxd[v], ops[i].D.r);
                 }
-                pg.launches.push_back(mk(1, first, nj, 0, 0, maxd, 0, 0, cls, L, wait));
-                // one launch per panel and kernel shape (plus one that applies the last panel)
+                // one launch per panel and kernel shape, plus the one that applies
+                // the last panel and writes the results; the first carries the
+                // wait on the other stream
                 const int npanels = (maxd + kInvNB - 1) / kInvNB;
+                bool first_launch = true;
                 for (int p = 0; p <= npanels; ++p) {
                     size_t off = first;
                     for (int v = 0; v < 3; ++v) {
-                        if (vcount[v] > 0 && p <= (vmaxd[v] + kInvNB - 1) / kInvNB)
-                            pg.launches.push_back(mk(6, off, vcount[v], vmaxd[v], 0, v, p, 0, cls, L, -1));
+                        if (vcount[v] > 0 && p <= (vmaxd[v] + kInvNB - 1) / kInvNB) {
+                            pg.launches.push_back(mk(6, off, vcount[v], vmaxd[v], 0, v, p, 0, cls, L,
+                                                     first_launch ? wait : -1));
+                            first_launch = false;
+                        }
                         off += vcount[v];
                     }
                 }
-                pg.launches.push_back(mk(3, first, nj, 0, 0, maxd, 0, 0, cls, L, -1));
+                (void)nj;
             }
             // products, per precision
             for (int mx = 0; mx < 2; ++mx) {
@@ -1059,12 +1073,7 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                 const double pnc = L.panel > 0 ? std::min(kInvNB, j.d - (L.panel - 1) * kInvNB) : 0;
                 const double nc = L.panel < np ? std::min(kInvNB, j.d - L.panel * kInvNB) : 0;
                 L.flops += 8.0 * ((double)j.d * j.d * pnc + (double)j.d * nc * nc);
-                L.bytes += 16.0 * (2.0 * j.d * j.d + 2.0 * j.d * kInvNB);
-            }
-        } else if (L.type == 1 || L.type == 3) {
-            for (int q = 0; q < L.count; ++q) {
-                const InvJob& j = pg.inv[L.off + q];
-                L.bytes += 32.0 * j.d * j.d;
+                L.bytes += 16.0 * (2.0 * j.d * j.d + (double)j.d * kInvNB);
             }
         } else if (L.type == 4) {
             for (int q = 0; q < L.count; ++q) {
@@ -1155,6 +1164,10 @@ bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
     if (d->b > kInvMaxDim || d->a > kInvMaxDim) { msg = "block sizes above 1024 are not supported"; return false; }
     if (d->n > 65535) { msg = "n above 65535 is not supported"; return false; }
     if (d->precision != BT_FP64 && d->precision != BT_MIXED) { msg = "unknown precision"; return false; }
+    if ((d->flags & BT_DIAG_ONLY) && d->precision == BT_MIXED) {
+        msg = "BT_DIAG_ONLY needs BT_FP64: the mixed path's error estimate reads the off-diagonal blocks";
+        return false;
+    }
     const int P = d->partitions;
     if (P < 1) { msg = "partitions must be >= 1"; return false; }
     Dims D{d->n, d->b, d->a};
@@ -1198,6 +1211,7 @@ bool build_instances(std::vector<Instance>& inst, const std::vector<int>& sel, M
         bd.check = mixed_handle;
         bd.plain = (I.desc.flags & BT_PLAIN) != 0;
         bd.antiH = (I.desc.flags & BT_SIGMA_ANTIHERMITIAN) != 0;
+        bd.diag_only = (I.desc.flags & BT_DIAG_ONLY) != 0;
         bd.instance = i;
         if (!dry) {
             if (A) bd.Aext = A[i];
@@ -1251,8 +1265,6 @@ void collect_profile(bt_si_sq_plan* h) {
 int kernel_kind(const Launch& L) {
     switch (L.type) {
         case 0: return L.mixed ? BT_KERNEL_PRODUCT_MIXED : BT_KERNEL_PRODUCT_FP64;
-        case 1: return BT_KERNEL_INV_INIT;
-        case 3: return BT_KERNEL_INV_FINISH;
         case 5: return BT_KERNEL_NORM;
         case 6: return BT_KERNEL_INV_PANEL;
         default: return BT_KERNEL_SUM;
@@ -1324,8 +1336,6 @@ hipError_t enqueue_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, hipStream
         }
         switch (L.type) {
             case 0: e = launch_gemm_shape(dg + L.off, L.count, L.tiles, L.mixed != 0, L.shape, s); break;
-            case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
-            case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
             case 4: e = launch_add(da + L.off, L.count, L.maxelems, s); break;
             case 5: e = launch_norms(dn + L.off, L.count, s); break;
             case 6: e = launch_inv_step(dj + L.off, L.count, L.maxd, L.panel, L.tiles, h->status, s); break;
@@ -1547,9 +1557,17 @@ bt_status run_instances(bt_si_sq_plan* h, Mode mode, const std::vector<int>& sel
     return BT_OK;
 }
 
-bool check_blocks(const Dims& D, const bt_blocks* m, bool need, std::string& msg, const char* name) {
+bool check_blocks(const Dims& D, const bt_blocks* m, bool need, std::string& msg, const char* name,
+                  bool diag_only = false) {
     if (!m) {
         if (need) { msg = std::string(name) + " is null"; return false; }
+        return true;
+    }
+    if (diag_only) {
+        if (!m->diag || (D.a > 0 && !m->tip)) {
+            msg = std::string(name) + ": diag (and tip for a > 0) pointers missing";
+            return false;
+        }
         return true;
     }
     if (!m->diag || (D.n > 1 && (!m->upper || !m->lower))) {
@@ -1563,12 +1581,15 @@ bool check_blocks(const Dims& D, const bt_blocks* m, bool need, std::string& msg
     return true;
 }
 
-bool check_optional_blocks(const Dims& D, const bt_blocks* m, std::string& msg, const char* name) {
+bool check_optional_blocks(const Dims& D, const bt_blocks* m, std::string& msg, const char* name,
+                           bool diag_only = false) {
     if (!m) return true;
     const bool any = m->diag || m->upper || m->lower || m->arrow_right || m->arrow_bottom || m->tip;
     if (!any) return true;   // all null: X^R stays in the workspace
-    return check_blocks(D, m, true, msg, name);
+    return check_blocks(D, m, true, msg, name, diag_only);
 }
+
+bool diag_only_of(const Instance& I) { return (I.desc.flags & BT_DIAG_ONLY) != 0; }
 
 // Validate descriptors and size the workspace of a batch (dry run).
 bt_status plan_instances(int count, const bt_desc* descs, std::vector<Instance>& inst,
@@ -1706,7 +1727,7 @@ bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR) 
     if (h->inst.size() != 1) return set_err(h, BT_ERR_INVALID, "factor takes a single-instance handle");
     Instance& I = h->inst[0];
     std::string msg;
-    if (!check_blocks(I.D, A, true, msg, "A") || !check_optional_blocks(I.D, XR, msg, "XR"))
+    if (!check_blocks(I.D, A, true, msg, "A") || !check_optional_blocks(I.D, XR, msg, "XR", diag_only_of(I)))
         return set_err(h, BT_ERR_INVALID, msg);
     bt_status st = run_instances(h, MODE_FACTOR, {0}, A, nullptr, XR, nullptr, nullptr, nullptr);
     if (st == BT_OK) {
@@ -1726,7 +1747,7 @@ bt_status bt_si_sq_selected_solve(bt_si_sq_handle h, const bt_blocks* B, bt_bloc
     Instance& I = h->inst[0];
     if (!I.factored) return set_err(h, BT_ERR_STATE, "selected_solve before factor");
     std::string msg;
-    if (!check_blocks(I.D, B, true, msg, "B") || !check_blocks(I.D, XL, true, msg, "XL"))
+    if (!check_blocks(I.D, B, true, msg, "B") || !check_blocks(I.D, XL, true, msg, "XL", diag_only_of(I)))
         return set_err(h, BT_ERR_INVALID, msg);
     return run_instances(h, MODE_SQ, {0}, &I.A_used, B, &I.XR_used, XL, err_estimate, used_fp64_fallback);
 }
@@ -1749,9 +1770,10 @@ bt_status bt_si_sq_batch_solve(bt_si_sq_handle h, const bt_blocks* A, const bt_b
     std::string msg;
     for (int i = 0; i < count; ++i) {
         const Dims& D = h->inst[i].D;
+        const bool dg = diag_only_of(h->inst[i]);
         if (!check_blocks(D, &A[i], true, msg, "A") || !check_blocks(D, &B[i], true, msg, "B") ||
-            !check_optional_blocks(D, XR ? &XR[i] : nullptr, msg, "XR") ||
-            !check_blocks(D, &XL[i], true, msg, "XL")) {
+            !check_optional_blocks(D, XR ? &XR[i] : nullptr, msg, "XR", dg) ||
+            !check_blocks(D, &XL[i], true, msg, "XL", dg)) {
             if (count > 1) msg = "instance " + std::to_string(i) + ": " + msg;
             return set_err(h, BT_ERR_INVALID, msg);
         }
@@ -1784,7 +1806,7 @@ bt_status bt_si_sq_batch_selected_solve(bt_si_sq_handle h, const bt_blocks* B, b
         if (!I.factored) {
             return set_err(h, BT_ERR_STATE, "instance " + std::to_string(i) + ": selected_solve before factor");
         }
-        if (!check_blocks(I.D, &B[i], true, msg, "B") || !check_blocks(I.D, &XL[i], true, msg, "XL"))
+        if (!check_blocks(I.D, &B[i], true, msg, "B") || !check_blocks(I.D, &XL[i], true, msg, "XL", diag_only_of(I)))
             return set_err(h, BT_ERR_INVALID, "instance " + std::to_string(i) + ": " + msg);
         sel.push_back(i);
     }
@@ -2096,8 +2118,6 @@ bt_status bt_si_sq_diag_inverse(const void* src, void* dst, int32_t d, int32_t c
         if (e != hipSuccess) break;
         switch (L.type) {
             case 0: e = launch_gemm_shape(dg + L.off, L.count, L.tiles, L.mixed != 0, L.shape, s); break;
-            case 1: e = launch_inv_init(dj + L.off, L.count, L.maxd, s); break;
-            case 3: e = launch_inv_finish(dj + L.off, L.count, L.maxd, s); break;
             case 6: e = launch_inv_step(dj + L.off, L.count, L.maxd, L.panel, L.tiles, st, s); break;
             default: break;
         }
@@ -2129,6 +2149,7 @@ extern "C" size_t bt_si_sq_diag_schedule(const bt_desc* desc, char* out, size_t 
     bd.mode = MODE_BOTH;
     bd.mixed_bulk = desc->precision == BT_MIXED;
     bd.antiH = (desc->flags & BT_SIGMA_ANTIHERMITIAN) != 0;
+    bd.diag_only = (desc->flags & BT_DIAG_ONLY) != 0;
     bd.ws = reinterpret_cast<char*>((uintptr_t)1 << 40);
     bd.build();
     const int nl = levelize(bd.ops);

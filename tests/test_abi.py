@@ -241,3 +241,20 @@ def test_noalloc_inverse_rejects_requests_beyond_its_scratch():
     assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 1025, 1, C.byref(bad), None) == BT_ERR_INVALID
     assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 64, -1, C.byref(bad), None) == BT_ERR_INVALID
     assert L.bt_si_sq_diag_inverse_noalloc(fake, fake, 64, 0, C.byref(bad), None) == BT_OK
+
+
+def test_diag_only_flop_model_and_mixed_rejection():
+    """BT_DIAG_ONLY drops, per sequential BT step, the two products whose
+    results nothing reads (X^R_{k,k+1} and X^<_{k+1,k}): 22 instead of 24
+    b^3 units per step plus the last step's 3.  With BT_MIXED it is refused."""
+    from paper_2601_04904_amd import _lib as LB
+    L = _lib.lib()
+    for n, b in [(16, 32), (5, 7), (64, 512)]:
+        d = LB.make_desc(n, b, 0, 1, None, flags=LB.BT_DIAG_ONLY)
+        ex, us = C.c_double(), C.c_double()
+        assert L.bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)) == 0
+        assert ex.value == pytest.approx(8.0 * b ** 3 * (22 * (n - 1) + 3), rel=1e-12)
+        assert us.value == ex.value
+    d = LB.make_desc(8, 16, 0, 1, None, precision=LB.BT_MIXED, flags=LB.BT_DIAG_ONLY)
+    assert L.bt_si_sq_workspace_bytes(C.byref(d)) == 0
+    assert b"BT_DIAG_ONLY" in L.bt_si_sq_last_error(None)
