@@ -5,52 +5,69 @@ sharing one BT/BTA pattern and only the entries of X on that pattern wanted.
 The dense approach of Sec. II-C (Alg. 4) computes X in full and then keeps the
 pattern; that is what this module does, with LAPACK's inverse as the one
 library step.  Cost O(N^3), memory O(N^2): tiny and small inputs only.
+Blocks may differ in size (Sec. II-A: RGF applies unchanged to diagonal blocks
+of different sizes); then every block field is a list of blocks.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .blocks import Sel
+from .blocks import Sel, block_sizes, tip_size, uniform
+
+
+def _offsets(sizes):
+    off = [0]
+    for sz in sizes:
+        off.append(off[-1] + sz)
+    return off
 
 
 def assemble(M) -> np.ndarray:
-    """Dense N x N matrix (N = n b + a) from block storage; tip rows/cols last."""
-    n, b = M.diag.shape[0], M.diag.shape[1]
-    a = M.tip.shape[0]
-    N = n * b + a
+    """Dense N x N matrix (N = sum of the block sizes + a) from block storage;
+    tip rows/cols last.  Blocks may differ in size (lists of blocks)."""
+    sizes = block_sizes(M)
+    n = len(sizes)
+    a = tip_size(M)
+    off = _offsets(sizes)
+    nb = off[-1]
+    N = nb + a
     D = np.zeros((N, N), dtype=np.complex128)
     for i in range(n):
-        r = slice(i * b, (i + 1) * b)
+        r = slice(off[i], off[i + 1])
         D[r, r] = M.diag[i]
         if i < n - 1:
-            r1 = slice((i + 1) * b, (i + 2) * b)
+            r1 = slice(off[i + 1], off[i + 2])
             D[r, r1] = M.upper[i]
             D[r1, r] = M.lower[i]
         if a > 0:
-            t = slice(n * b, N)
+            t = slice(nb, N)
             D[r, t] = M.arrow_right[i]
             D[t, r] = M.arrow_bottom[i]
     if a > 0:
-        D[n * b:, n * b:] = M.tip
+        D[nb:, nb:] = M.tip
     return D
 
 
-def extract(X: np.ndarray, n: int, b: int, a: int) -> Sel:
-    """The entries of a dense X on the BT/BTA pattern."""
-    out = Sel.zeros(n, b, a)
+def extract(X: np.ndarray, n, b, a: int) -> Sel:
+    """The entries of a dense X on the BT/BTA pattern.  b is the block size,
+    or the list of the n block sizes (then every field is a list)."""
+    sizes = list(b) if np.ndim(b) > 0 else [int(b)] * n
+    out = Sel.zeros(n, sizes[0] if n else 0, a) if np.ndim(b) == 0 else Sel.zeros_var(sizes, a)
+    off = _offsets(sizes)
+    nb = off[-1]
     for i in range(n):
-        r = slice(i * b, (i + 1) * b)
+        r = slice(off[i], off[i + 1])
         out.diag[i] = X[r, r]
         if i < n - 1:
-            r1 = slice((i + 1) * b, (i + 2) * b)
+            r1 = slice(off[i + 1], off[i + 2])
             out.upper[i] = X[r, r1]
             out.lower[i] = X[r1, r]
         if a > 0:
-            t = slice(n * b, n * b + a)
+            t = slice(nb, nb + a)
             out.arrow_right[i] = X[r, t]
             out.arrow_bottom[i] = X[t, r]
     if a > 0:
-        out.tip[:] = X[n * b:, n * b:]
+        out.tip[:] = X[nb:, nb:]
     return out
 
 
@@ -59,8 +76,9 @@ def solve_dense(A, B=None):
 
     With B None only X^R is returned (as (X^R, None)).
     """
-    n, b = A.diag.shape[0], A.diag.shape[1]
-    a = A.tip.shape[0]
+    sizes = block_sizes(A)
+    n, a = len(sizes), tip_size(A)
+    b = sizes[0] if uniform(sizes) and n > 0 else sizes
     G = np.linalg.inv(assemble(A))
     XR = extract(G, n, b, a)
     if B is None:

@@ -29,6 +29,7 @@ from __future__ import annotations
 import numpy as np
 
 from .blocks import Sel
+from .blocks import block_sizes, tip_size, uniform
 from .rgf import backward_step, forward_step, from_dicts, rgf_bta, to_dicts
 
 
@@ -76,29 +77,31 @@ class _Reduced:
 
     def __init__(self, M, nodes, a):
         m = len(nodes)
-        self.diag = np.array([M[(r, r)] for r in nodes])
-        self.upper = np.array([M.get((nodes[j], nodes[j + 1]),
-                                     np.zeros_like(M[(nodes[j], nodes[j])]))
-                               for j in range(m - 1)])
-        self.lower = np.array([M.get((nodes[j + 1], nodes[j]),
-                                     np.zeros_like(M[(nodes[j], nodes[j])]))
-                               for j in range(m - 1)])
-        b = self.diag.shape[1]
+        dims = [M[(r, r)].shape[0] for r in nodes]
+        pack = np.array if uniform(dims) else list
+
+        def z(r, c):
+            return np.zeros((r, c), np.complex128)
+        self.diag = pack([M[(r, r)] for r in nodes])
+        self.upper = pack([M.get((nodes[j], nodes[j + 1]), z(dims[j], dims[j + 1]))
+                           for j in range(m - 1)])
+        self.lower = pack([M.get((nodes[j + 1], nodes[j]), z(dims[j + 1], dims[j]))
+                           for j in range(m - 1)])
         if a > 0:
-            self.arrow_right = np.array([M[(r, "t")] for r in nodes])
-            self.arrow_bottom = np.array([M[("t", r)] for r in nodes])
+            self.arrow_right = pack([M[(r, "t")] for r in nodes])
+            self.arrow_bottom = pack([M[("t", r)] for r in nodes])
             self.tip = np.array(M[("t", "t")])
         else:
-            self.arrow_right = np.zeros((m, b, 0), np.complex128)
-            self.arrow_bottom = np.zeros((m, 0, b), np.complex128)
+            self.arrow_right = pack([z(dims[j], 0) for j in range(m)])
+            self.arrow_bottom = pack([z(0, dims[j]) for j in range(m)])
             self.tip = np.zeros((0, 0), np.complex128)
 
 
 def _forward_partitions(A, B, bounds):
-    n, b = A.diag.shape[0], A.diag.shape[1]
-    a = A.tip.shape[0]
+    sizes = block_sizes(A)
+    n, a = len(sizes), tip_size(A)
     quad = B is not None
-    dim = {i: b for i in range(n)}
+    dim = {i: sizes[i] for i in range(n)}
     dim["t"] = a
     At = to_dicts(A, n, a)
     Bt = to_dicts(B, n, a) if quad else {}
@@ -129,7 +132,7 @@ def _forward_partitions(A, B, bounds):
 
 def reduced_system(A, B, bounds):
     """(reduced A, reduced B, nodes) after the partition eliminations."""
-    a = A.tip.shape[0]
+    a = tip_size(A)
     At, Bt, _, reduced, _ = _forward_partitions(A, B, bounds)
     Ar = _Reduced(At, reduced, a)
     Br = _Reduced(Bt, reduced, a) if B is not None else None
@@ -137,9 +140,11 @@ def reduced_system(A, B, bounds):
 
 
 def prgf(A, B, bounds, reduced_split=False):
-    """Partitioned SI (+ SQ when B is given).  Returns (X^R, X^<) as Sel."""
-    n, b = A.diag.shape[0], A.diag.shape[1]
-    a = A.tip.shape[0]
+    """Partitioned SI (+ SQ when B is given).  Returns (X^R, X^<) as Sel.
+    Blocks may differ in size (Sec. II-A)."""
+    sizes = block_sizes(A)
+    n, a = len(sizes), tip_size(A)
+    b = sizes
     quad = B is not None
     At, Bt, recs, reduced, dim = _forward_partitions(A, B, bounds)
     XR, XL = {}, {}

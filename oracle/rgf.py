@@ -29,19 +29,28 @@ from __future__ import annotations
 
 import numpy as np
 
-from .blocks import Sel
+from .blocks import Sel, block_sizes, tip_size, uniform
 
 
 def _H(M: np.ndarray) -> np.ndarray:
     return M.conj().T
 
 
+def _sel_zeros(sizes, a):
+    """Uniform blocks as 3-D arrays, blocks of different sizes as lists."""
+    if uniform(sizes):
+        return Sel.zeros(len(sizes), sizes[0] if sizes else 0, a)
+    return Sel.zeros_var(sizes, a)
+
+
 def rgf_bt(A, B=None):
     """Alg. 1 + Alg. 2 for a BT matrix (the arrowhead, if any, is ignored).
+    Blocks may differ in size (Sec. II-A).
 
     Returns (X^R, X^<) as Sel; X^< is None when B is None.
     """
-    n, b = A.diag.shape[0], A.diag.shape[1]
+    sizes = block_sizes(A)
+    n = len(sizes)
     quad = B is not None
     Ad = [np.array(A.diag[i], dtype=np.complex128) for i in range(n)]
     Bd = [np.array(B.diag[i], dtype=np.complex128) for i in range(n)] if quad else None
@@ -62,8 +71,8 @@ def rgf_bt(A, B=None):
         SB[n - 1] = SA[n - 1] @ Bd[n - 1] @ _H(SA[n - 1])
 
     # Alg. 2: backward pass.
-    XR = Sel.zeros(n, b, 0)
-    XL = Sel.zeros(n, b, 0) if quad else None
+    XR = _sel_zeros(sizes, 0)
+    XL = _sel_zeros(sizes, 0) if quad else None
     XR.diag[n - 1] = SA[n - 1]
     if quad:
         XL.diag[n - 1] = SB[n - 1]
@@ -176,7 +185,10 @@ def to_dicts(M, n, a):
 
 
 def from_dicts(X, n, b, a) -> Sel:
-    out = Sel.zeros(n, b, a)
+    """Sel of the pattern blocks of a block dict; b is the block size or the
+    list of block sizes."""
+    sizes = list(b) if np.ndim(b) > 0 else [int(b)] * n
+    out = _sel_zeros(sizes, a)
     for i in range(n):
         out.diag[i] = X[(i, i)]
         if i < n - 1:
@@ -196,10 +208,10 @@ def rgf_bta(A, B=None):
     Block i is eliminated against N(i) = {i+1, t} (i+1 absent for the last
     block, t absent when a == 0).  Returns (X^R, X^<) as Sel.
     """
-    n, b = A.diag.shape[0], A.diag.shape[1]
-    a = A.tip.shape[0]
+    sizes = block_sizes(A)
+    n, a = len(sizes), tip_size(A)
     quad = B is not None
-    dim = {i: b for i in range(n)}
+    dim = {i: sizes[i] for i in range(n)}
     dim["t"] = a
     At = to_dicts(A, n, a)
     Bt = to_dicts(B, n, a) if quad else {}
@@ -215,4 +227,4 @@ def rgf_bta(A, B=None):
     XR, XL = {}, {}
     for rec in reversed(recs):
         backward_step(rec, XR, XL, quad)
-    return from_dicts(XR, n, b, a), (from_dicts(XL, n, b, a) if quad else None)
+    return from_dicts(XR, n, sizes, a), (from_dicts(XL, n, sizes, a) if quad else None)

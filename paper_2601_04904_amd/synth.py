@@ -33,8 +33,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "BTA", "gen_A", "gen_B", "gen_problem", "CONFIGS", "config_problem",
-    "batch_specs", "serving_trace", "equilibrium_B", "perturb",
+    "BTA", "VBTA", "gen_A", "gen_B", "gen_problem", "gen_problem_var", "ramp_sizes",
+    "CONFIGS", "VAR_CONFIGS", "config_problem", "batch_specs", "serving_trace",
+    "equilibrium_B", "perturb",
 ]
 
 
@@ -77,6 +78,48 @@ class BTA:
         return BTA(np.zeros((n, b, b), dtype), np.zeros((max(n - 1, 0), b, b), dtype),
                    np.zeros((max(n - 1, 0), b, b), dtype), np.zeros((n, b, a), dtype),
                    np.zeros((n, a, b), dtype), np.zeros((a, a), dtype))
+
+
+@dataclass
+class VBTA:
+    """Block storage with diagonal blocks of different sizes (Sec. II-A: RGF
+    applies unchanged when the blocks differ in size, e.g. a device whose
+    cross-section varies between source and drain).  Every field is a list of
+    2-D complex128 blocks: diag[i] is sizes[i] x sizes[i], upper[i] is
+    sizes[i] x sizes[i+1], lower[i] is sizes[i+1] x sizes[i], arrow_right[i]
+    is sizes[i] x a, arrow_bottom[i] is a x sizes[i], tip is a x a."""
+    diag: list
+    upper: list
+    lower: list
+    arrow_right: list
+    arrow_bottom: list
+    tip: np.ndarray
+
+    @property
+    def sizes(self):
+        return [int(d.shape[0]) for d in self.diag]
+
+    @property
+    def n(self) -> int:
+        return len(self.diag)
+
+    @property
+    def a(self) -> int:
+        return self.tip.shape[0]
+
+    def fields(self):
+        return (self.diag, self.upper, self.lower, self.arrow_right,
+                self.arrow_bottom, self.tip)
+
+    @staticmethod
+    def zeros(sizes, a: int, dtype=np.complex128) -> "VBTA":
+        n = len(sizes)
+        return VBTA([np.zeros((sizes[i], sizes[i]), dtype) for i in range(n)],
+                    [np.zeros((sizes[i], sizes[i + 1]), dtype) for i in range(n - 1)],
+                    [np.zeros((sizes[i + 1], sizes[i]), dtype) for i in range(n - 1)],
+                    [np.zeros((sizes[i], a), dtype) for i in range(n)],
+                    [np.zeros((a, sizes[i]), dtype) for i in range(n)],
+                    np.zeros((a, a), dtype))
 
 
 def _cn(rng: np.random.Generator, shape, var: float) -> np.ndarray:
@@ -143,6 +186,60 @@ def gen_problem(n: int, b: int, a: int = 0, E: float = 0.3, eta: float = 1e-3,
     return A, B
 
 
+def gen_problem_var(sizes, a: int = 0, E: float = 0.3, eta: float = 1e-3, seed: int = 0):
+    """(A, B) with diagonal blocks of the given sizes: the recipe above with b
+    replaced by the size of the block at hand, and the couplings scaled by
+    the geometric mean of the two sizes they join (T_i complex
+    N(0, 0.5/sqrt(b_i b_{i+1})), b_i x b_{i+1}).  Same draw order as
+    gen_problem; with equal sizes the values equal gen_problem's."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(sizes)
+    z = E + 1j * eta
+    A = VBTA.zeros(sizes, a)
+    for i in range(n):
+        b = sizes[i]
+        A.diag[i] = z * np.eye(b) - _hermitian(rng, b)
+        if i < n - 1:
+            T = _cn(rng, (b, sizes[i + 1]), 0.5 / np.sqrt(b * sizes[i + 1]))
+            A.upper[i] = -T
+            A.lower[i] = -T.conj().T
+    A.diag[0] += 0.5j * np.eye(sizes[0])
+    if n > 1:
+        A.diag[n - 1] += 0.5j * np.eye(sizes[n - 1])
+    if a > 0:
+        for i in range(n):
+            K = _cn(rng, (sizes[i], a), 0.1 / sizes[i])
+            A.arrow_right[i] = -K
+            A.arrow_bottom[i] = -K.conj().T
+        A.tip[:] = z * np.eye(a) - _hermitian(rng, a) + 0.5j * np.eye(a)
+    B = VBTA.zeros(sizes, a)
+    for i in range(n):
+        C = _cn(rng, (sizes[i], sizes[i]), 1.0)
+        B.diag[i] = 1j * (C @ C.conj().T) / sizes[i]
+        if i < n - 1:
+            D = _cn(rng, (sizes[i], sizes[i + 1]), 1.0)
+            B.upper[i] = 0.1j * D
+            B.lower[i] = 0.1j * D.conj().T
+    if a > 0:
+        for i in range(n):
+            F = _cn(rng, (sizes[i], a), 1.0)
+            B.arrow_right[i] = 0.1j * F
+            B.arrow_bottom[i] = 0.1j * F.conj().T
+        Ct = _cn(rng, (a, a), 1.0)
+        B.tip[:] = 1j * (Ct @ Ct.conj().T) / a
+    return A, B
+
+
+def ramp_sizes(n: int, lo: int, hi: int, steps: int):
+    """Block sizes of a device whose cross-section widens from the contacts
+    (size lo) to the channel (size hi) over `steps` blocks at each end."""
+    out = []
+    for i in range(n):
+        j = min(i, n - 1 - i, steps)
+        out.append(int(lo + (hi - lo) * j // steps))
+    return out
+
+
 def equilibrium_B(A: BTA, c: complex = 1.0) -> BTA:
     """B = c (A^H - A) restricted to the pattern (anti-Hermitian for real c).
 
@@ -197,10 +294,26 @@ CONFIGS = {
     "bt_n16_b32": ProblemConfig("bt_n16_b32", 16, 32, 0, 0.3, 1e-3, 0, (1, 2, 4)),
     "bt_n64_b512": ProblemConfig("bt_n64_b512", 64, 512, 0, 0.3, 1e-4, 0, (1, 8)),
     "bta_n128_b384_a512": ProblemConfig("bta_n128_b384_a512", 128, 384, 512, 0.3, 1e-3, 0, (16,)),
+    # the synthetic-device (SD) weak-scaling series of Sec. IV at its one-GPU
+    # size: n = 32 diagonal blocks of b = 1024 (same input recipe)
+    "sd_n32_b1024": ProblemConfig("sd_n32_b1024", 32, 1024, 0, 0.3, 1e-3, 0, (1, 2, 4)),
+}
+
+# Diagonal blocks of different sizes (Sec. II-A): a device whose cross-section
+# widens from 256 at the contacts to 512 in the channel over 4 blocks at each
+# end (n = 48), without and with an arrowhead of 256.
+VAR_CONFIGS = {
+    "vb_n48_b256to512": dict(sizes=ramp_sizes(48, 256, 512, 4), a=0, E=0.3, eta=1e-3, seed=0,
+                             partitions=(1, 4)),
+    "vbta_n48_b256to512_a256": dict(sizes=ramp_sizes(48, 256, 512, 4), a=256, E=0.3, eta=1e-3,
+                                    seed=0, partitions=(1, 4)),
 }
 
 
 def config_problem(name: str):
+    if name in VAR_CONFIGS:
+        c = VAR_CONFIGS[name]
+        return gen_problem_var(c["sizes"], c["a"], c["E"], c["eta"], c["seed"])
     c = CONFIGS[name]
     return gen_problem(c.n, c.b, c.a, c.E, c.eta, c.seed)
 

@@ -14,7 +14,13 @@ def blocks_of(X):
     """List of (name, index, block) over the selected blocks of X."""
     out = []
     for f in FIELDS:
-        arr = np.asarray(getattr(X, f))
+        val = getattr(X, f)
+        if isinstance(val, (list, tuple)):       # blocks of different sizes
+            for i, blk in enumerate(val):
+                if np.size(blk):
+                    out.append((f, i, np.asarray(blk)))
+            continue
+        arr = np.asarray(val)
         if arr.size == 0:
             continue
         if f == "tip":
