@@ -90,6 +90,27 @@ def measured_traffic(kernel, workload, partitions):
         return None
 
 
+def oracle_floor(workload, partitions):
+    """What the oracle alone says about FP64 rounding on this workload (stored
+    by tests/golden/make_fullsize_floors.py, which calls only the oracle):
+    the spread of two oracle evaluations of the reported form whose rounding
+    differs ("floor") and the oracle's own difference between this form's
+    ordering and the sequential sweep ("vs_sequential"), which bounds what a
+    correct GPU result can be held to against the sequential oracle."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, "tests", "golden", f"fullsize_floors_{workload}.json")) as f:
+            rec = json.load(f)["forms"].get(f"P{partitions}")
+    except (OSError, ValueError, KeyError):
+        return None
+    if not rec:
+        return None
+    out = {"floor": rec.get("floor")}
+    if "vs_sequential" in rec:
+        out["vs_sequential"] = rec["vs_sequential"]
+    return out
+
+
 def cpu_baseline(A, B, seconds, XR_gpu, XL_gpu):
     """The oracle (sequential RGF, NumPy complex128) on the host cores, bounded sample."""
     import numpy as np
@@ -109,24 +130,23 @@ def cpu_baseline(A, B, seconds, XR_gpu, XL_gpu):
         if t_total / n_done * (n_done + 1) > 2.0 * seconds:
             break
     # parity of the timed GPU result against this oracle run (same inputs)
+    def blocks(M, f):
+        v = getattr(M, f)
+        if isinstance(v, (list, tuple)):                    # blocks of different sizes
+            return [np.asarray(x) for x in v if np.size(x)]
+        v = np.asarray(v)
+        if v.size == 0:
+            return []
+        return [v] if v.ndim == 2 else list(v)
+
     def rel(X, R):
         worst = 0.0
         fields = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
-        big = 0.0
+        big = max((np.linalg.norm(r) for f in fields for r in blocks(R, f)), default=0.0)
         for f in fields:
-            r = np.asarray(getattr(R, f))
-            if r.size:
-                big = max(big, max(np.linalg.norm(x) for x in r.reshape(-1, *r.shape[-2:])))
-        for f in fields:
-            r = np.asarray(getattr(R, f))
-            if r.size == 0:
-                continue
-            x = np.asarray(getattr(X, f))
-            if r.ndim == 2:
-                r, x = r[None], x[None]
-            for i in range(r.shape[0]):
-                den = max(np.linalg.norm(r[i]), 1e-6 * big)
-                worst = max(worst, float(np.linalg.norm(x[i] - r[i]) / den))
+            for x, r in zip(blocks(X, f), blocks(R, f)):
+                den = max(np.linalg.norm(r), 1e-6 * big)
+                worst = max(worst, float(np.linalg.norm(x - r) / den))
         return worst
     errR = rel(XR_gpu, res[0])
     errL = rel(XL_gpu, res[1])
@@ -231,31 +251,41 @@ def bench_batch(args, torch, S):
 
 
 def bench_serve(args, torch, S):
-    """Poisson serving trace through the continuous-batching engine vs plain RGF."""
+    """Poisson serving trace through the continuous-batching engine vs plain RGF:
+    the configured rate (saturating one GPU), then, with --unsaturated-factor,
+    the same requests at that fraction of the capacity the first run measured."""
     from paper_2601_04904_amd import serving
     from paper_2601_04904_amd.synth import serving_trace
-    trace = serving_trace(args.requests, rate=args.rate, seed=0,
-                          n_range=(16, args.serve_max_n), b_choices=tuple(range(128, args.serve_max_b + 1, 64)))
-    reqs = serving.requests_from_trace(trace)
     budget = int(args.serve_budget_gb * 1e9)
-    eng = serving.ServingEngine(budget_bytes=budget, max_inflight=args.inflight, max_wave=args.max_wave,
-                                router=serving.PrecisionRouter(probe_max_flops=args.probe_max_tflop * 1e12))
-    stats = eng.replay(reqs)
-    stats["waves"] = eng.waves
-    stats["errors"] = eng.errors
-    stats["routed_to_fp64"] = eng.router.routed
-    stats["oom_retries"] = eng.oom_retries
-    log(f"[bench] serving: {stats}")
-    # plain RGF on the same trace: FP64 only, one request at a time, one launch per product
-    plain_reqs = serving.requests_from_trace(trace)
-    for r in plain_reqs:
-        r.precision = "fp64"
-        r.flags = S.BT_PLAIN
-    peng = serving.ServingEngine(budget_bytes=budget, max_inflight=1, max_wave=1)
-    pstats = peng.replay(plain_reqs)
-    log(f"[bench] plain RGF serving: {pstats}")
+
+    def run(rate):
+        trace = serving_trace(args.requests, rate=rate, seed=0, n_range=(16, args.serve_max_n),
+                              b_choices=tuple(range(128, args.serve_max_b + 1, 64)))
+        reqs = serving.requests_from_trace(trace, partitions=serving.auto_partitions)
+        eng = serving.ServingEngine(budget_bytes=budget, max_inflight=args.inflight, max_wave=args.max_wave,
+                                    router=serving.PrecisionRouter(probe_max_flops=args.probe_max_tflop * 1e12),
+                                    log=log)
+        stats = eng.replay(reqs)
+        stats["waves"] = eng.waves
+        stats["errors"] = eng.errors
+        stats["routed_to_fp64"] = eng.router.routed
+        stats["oom_retries"] = eng.oom_retries
+        log(f"[bench] serving at {rate:g}/s: {stats}")
+        # plain RGF on the same trace: FP64, sequential sweep, one request at a
+        # time, one launch per single-term product, one stream
+        plain_reqs = serving.requests_from_trace(trace)
+        for r in plain_reqs:
+            r.precision = "fp64"
+            r.flags = S.BT_PLAIN
+        peng = serving.ServingEngine(budget_bytes=budget, max_inflight=1, max_wave=1, log=log)
+        pstats = peng.replay(plain_reqs)
+        log(f"[bench] plain RGF serving at {rate:g}/s: {pstats}")
+        ok = not eng.errors and not stats.get("failed")
+        return stats, pstats, ok
+
+    stats, pstats, ok = run(args.rate)
     # a run in which any wave failed has no valid throughput
-    value = round(stats["solves_per_s"], 4) if not eng.errors and not stats.get("failed") else None
+    value = round(stats["solves_per_s"], 4) if ok else None
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * stats["wall_s"], 1),
@@ -263,11 +293,22 @@ def bench_serve(args, torch, S):
         "data": "synthetic",
         "config": {"workload": f"serve_{args.requests}_poisson_{args.rate:g}", "n": f"U{{16..{args.serve_max_n}}}",
                    "b": f"U{{128..{args.serve_max_b}}} step 64", "a": "U{0,256,512}", "fp64_share": 0.3,
-                   "budget_gb": args.serve_budget_gb, "inflight": args.inflight},
+                   "budget_gb": args.serve_budget_gb, "inflight": args.inflight,
+                   "partitions": "2 per request (n >= 8), plain RGF sequential"},
         "latency_s": {"p50": stats["p50_s"], "p99": stats["p99_s"]},
         "serving": stats, "plain_rgf": pstats,
         "vs_plain_rgf_solves": round(stats["solves_per_s"] / pstats["solves_per_s"], 3) if pstats["solves_per_s"] else None,
     }
+    if args.unsaturated_factor > 0 and ok:
+        cap = stats["requests"] / stats["wall_s"]              # requests/s the engine sustained
+        rate2 = args.unsaturated_factor * cap
+        st2, ps2, ok2 = run(rate2)
+        out["unsaturated"] = {
+            "rate_per_s": round(rate2, 4), "of_capacity": args.unsaturated_factor,
+            "latency_s": {"p50": st2["p50_s"], "p99": st2["p99_s"]},
+            "serving": st2 if ok2 else None, "plain_rgf": ps2,
+            "vs_plain_rgf_solves": round(st2["solves_per_s"] / ps2["solves_per_s"], 3) if ps2["solves_per_s"] and ok2 else None,
+        }
     print(json.dumps(out), flush=True)
 
 
@@ -277,7 +318,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bt_n64_b512",
-                    help="bt_n16_b32 | bt_n64_b512 | bta_n128_b384_a512 | batch | serve | copy")
+                    help="bt_n16_b32 | bt_n64_b512 | bta_n128_b384_a512 | sd_n32_b1024 | "
+                         "vb_n48_b256to512 | vbta_n48_b256to512_a256 | batch | serve | copy")
     ap.add_argument("--partitions", type=int, default=None,
                     help="time only this partition count (default: every form the workload names)")
     ap.add_argument("--compare-partitions", type=int, nargs="*", default=None,
@@ -292,12 +334,14 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-wave", type=int, default=32)
     ap.add_argument("--plain-count", type=int, default=8)
-    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--unsaturated-factor", type=float, default=0.7,
+                    help="serve: also replay the trace at this fraction of the measured capacity (0: skip)")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--serve-max-n", type=int, default=256)
     ap.add_argument("--serve-max-b", type=int, default=1024)
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
-    ap.add_argument("--inflight", type=int, default=2)
+    ap.add_argument("--inflight", type=int, default=3)
     ap.add_argument("--max-wave", type=int, default=8)
     ap.add_argument("--antihermitian", type=int, default=1,
                     help="1: also time the reported form with BT_SIGMA_ANTIHERMITIAN (the synthetic "
@@ -315,7 +359,7 @@ def main():
     import numpy as np
     import torch
     from paper_2601_04904_amd import solver as S
-    from paper_2601_04904_amd.synth import CONFIGS, gen_problem
+    from paper_2601_04904_amd.synth import CONFIGS, VAR_CONFIGS, config_problem
 
     if not torch.cuda.is_available():
         log("no GPU visible")
@@ -345,24 +389,38 @@ def main():
         return bench_batch(args, torch, S)
     if args.workload == "serve":
         return bench_serve(args, torch, S)
-    cfg = CONFIGS[args.workload]
-    n, b, a = cfg.n, cfg.b, cfg.a
+    if args.workload in VAR_CONFIGS:
+        # diagonal blocks of different sizes (Sec. II-A)
+        vc = VAR_CONFIGS[args.workload]
+        sizes = list(vc["sizes"])
+        n, b, a = len(sizes), max(sizes), vc["a"]
+        cfg = argparse.Namespace(name=args.workload, E=vc["E"], eta=vc["eta"], seed=vc["seed"],
+                                 partitions=vc["partitions"])
+        Blocks = S.VarDeviceBlocks
+        new_blocks = lambda: S.VarDeviceBlocks.empty(sizes, a)
+    else:
+        cfg = CONFIGS[args.workload]
+        n, b, a = cfg.n, cfg.b, cfg.a
+        sizes = None
+        Blocks = S.DeviceBlocks
+        new_blocks = lambda: S.DeviceBlocks.empty(n, b, a)
     # the forms the workload names (e.g. sequential and P=8); the value is the
     # fastest of them, the others are reported beside it
     forms = [args.partitions] if args.partitions is not None else list(cfg.partitions)
     extra = [q for q in (args.compare_partitions or []) if q not in forms]
-    log(f"[bench] workload {cfg.name}: n={n} b={b} a={a} forms P={forms} extra P={extra} eta={cfg.eta}")
+    log(f"[bench] workload {cfg.name}: n={n} b={b if sizes is None else 'per block'} a={a} "
+        f"forms P={forms} extra P={extra} eta={cfg.eta}")
     t0 = time.perf_counter()
-    A, B = gen_problem(n, b, a, cfg.E, cfg.eta, cfg.seed)
+    A, B = config_problem(args.workload)
     log(f"[bench] generated inputs in {time.perf_counter() - t0:.1f} s")
-    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
-    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    dA, dB = Blocks.from_host(A), Blocks.from_host(B)
+    XR, XL = new_blocks(), new_blocks()
 
     timed = {}
     for P in forms + extra:
-        sol = S.Solver(n, b, a, partitions=P, flags=args.flags)
+        sol = S.Solver(n, b, a, partitions=P, flags=args.flags, sizes=sizes)
         el, lt = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
-        exP, usP = S.flops(n, b, a, P)
+        exP, usP = S.flops(n, b, a, P, sizes=sizes)
         timed[P] = dict(elapsed=el, lat=lt, launches=sol.last_launch_count(), ex=exP, us=usP)
         sol.destroy()
         log(f"[bench] P={P}: {1e3 * el / args.steps:.2f} ms/solve, {timed[P]['launches']} launches/solve")
@@ -373,7 +431,7 @@ def main():
 
     # roofline of the dominant kernel of the reported form, from HIP events
     # recorded around each launch on the stream it runs on
-    sol = S.Solver(n, b, a, partitions=P)
+    sol = S.Solver(n, b, a, partitions=P, sizes=sizes)
     sol.solve(dA, dB, XR, XL)
     sol.profile(True)
     for _ in range(args.profile_steps):
@@ -422,7 +480,7 @@ def main():
     # the same form with the anti-Hermitian Sigma^< option (not the value: it
     # assumes the structure of the input), with its difference to the general path
     ah = None
-    if args.antihermitian:
+    if args.antihermitian and sizes is None:
         XLg = XL.to_host()
         solh = S.Solver(n, b, a, partitions=P, flags=args.flags | S.BT_SIGMA_ANTIHERMITIAN)
         el_h, lat_h = time_solves(torch, solh, dA, dB, XR, XL, args.steps, args.warmup)
@@ -451,6 +509,9 @@ def main():
         XRh, XLh = XR.to_host(), XL.to_host()
         cpu, (eR, eL) = cpu_baseline(A, B, args.cpu_seconds, XRh, XLh)
         cpu["gpu_max_rel_err_vs_oracle"] = {"XR": eR, "XL": eL}
+        fl = oracle_floor(cfg.name, P)
+        if fl is not None:
+            cpu["oracle_floor"] = fl
         log(f"[bench] cpu {cpu['value']:.4f} solves/s on {cpu['cores']} threads; "
             f"GPU error vs oracle R={eR:.2e} L={eL:.2e}")
 
@@ -469,7 +530,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "n": n, "b": b, "a": a, "partitions": P,
+        "config": {"workload": cfg.name, "n": n, "b": b if sizes is None else sizes, "a": a,
+                   "partitions": P,
                    "E": cfg.E, "eta": cfg.eta, "seed": cfg.seed, "hip_graph": bool(args.graph),
                    "tile_shapes": "autotuned" if args.tuned else "default rule"},
         "tflops_executed": round(tflops_ex, 3),

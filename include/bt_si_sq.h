@@ -26,7 +26,11 @@
  *     arrow_bottom  n     blocks of a x b     M_{t,i}     (NULL when a == 0)
  *     tip           1     block  of a x a     M_{t,t}     (NULL when a == 0)
  * Blocks of one field are contiguous (block i starts at i * rows * cols
- * complex numbers).
+ * complex numbers).  With per-block sizes b_i (bt_desc.block_sizes) block i
+ * of diag is b_i x b_i, of upper b_i x b_{i+1}, of lower b_{i+1} x b_i, of
+ * arrow_right b_i x a and of arrow_bottom a x b_i, and block i of a field
+ * starts after the blocks 0..i-1 of that field (at sum_{j<i} b_j^2,
+ * sum_{j<i} b_j b_{j+1} and a sum_{j<i} b_j complex numbers).
  *
  * Ownership.  The caller owns A, B and the output blocks (device memory it
  * allocated).  The library never writes to A or B, and outputs must not
@@ -120,6 +124,10 @@ typedef struct {
     double tol;                 /* mixed path: re-run in FP64 when the error estimate
                                    exceeds tol (<= 0 selects 1e-4) */
     uint32_t flags;
+    const int32_t* block_sizes; /* host array of n diagonal-block sizes (each 1..1024),
+                                   or NULL for n blocks of size b.  RGF applies
+                                   unchanged to blocks of different sizes (Sec. II-A);
+                                   b is then ignored.  Read during the call only. */
 } bt_desc;
 
 typedef struct {

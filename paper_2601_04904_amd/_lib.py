@@ -37,7 +37,8 @@ KERNEL_NAMES = {0: "product_fp64", 1: "product_mixed", 2: "inv_panel", 3: "inv_i
 class bt_desc(C.Structure):
     _fields_ = [("n", C.c_int32), ("b", C.c_int32), ("a", C.c_int32),
                 ("partitions", C.c_int32), ("part_bounds", C.POINTER(C.c_int32)),
-                ("precision", C.c_int32), ("tol", C.c_double), ("flags", C.c_uint32)]
+                ("precision", C.c_int32), ("tol", C.c_double), ("flags", C.c_uint32),
+                ("block_sizes", C.POINTER(C.c_int32))]
 
 
 class bt_blocks(C.Structure):
@@ -147,15 +148,22 @@ def lib():
 
 
 def make_desc(n: int, b: int, a: int = 0, partitions: int = 1, bounds=None,
-              precision: int = BT_FP64, tol: float = 1e-4, flags: int = 0):
+              precision: int = BT_FP64, tol: float = 1e-4, flags: int = 0, sizes=None):
+    """bt_desc; sizes: per-block sizes (then b is ignored) or None."""
     d = bt_desc()
     d.n, d.b, d.a, d.partitions = n, b, a, partitions
     keep = None
     if bounds is not None:
         keep = (C.c_int32 * len(bounds))(*bounds)
         d.part_bounds = C.cast(keep, C.POINTER(C.c_int32))
+    keep_sizes = None
+    if sizes is not None:
+        if len(sizes) != n:
+            raise ValueError(f"sizes has {len(sizes)} entries, n = {n}")
+        keep_sizes = (C.c_int32 * n)(*[int(v) for v in sizes])
+        d.block_sizes = C.cast(keep_sizes, C.POINTER(C.c_int32))
     d.precision, d.tol, d.flags = precision, tol, flags
-    d._keep = keep  # keep the bounds array alive with the descriptor
+    d._keep = (keep, keep_sizes)  # keep the arrays alive with the descriptor
     return d
 
 

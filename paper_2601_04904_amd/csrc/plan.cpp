@@ -102,9 +102,37 @@ struct OpRec {
 
 enum Mode { MODE_FACTOR = 0, MODE_SQ = 1, MODE_BOTH = 2 };
 
+// Block structure of one instance: n diagonal blocks (all of size b, or of
+// the sizes in sz when the caller gives them; b is then the largest) and an
+// arrow tip of size a.  Blocks of one field are stored one after another, so
+// block i of a field starts at the sum of the sizes of blocks 0..i-1.
 struct Dims {
-    int n, b, a;
-    int dim(int u) const { return u == n ? a : b; }
+    int n = 0, b = 0, a = 0;
+    std::vector<int> sz;                  // per-block sizes, empty = uniform b
+    std::vector<size_t> od, oul, oar;     // element offsets: diag, upper/lower, arrows
+    Dims() = default;
+    Dims(int n_, int b_, int a_, const int32_t* sizes = nullptr) : n(n_), b(b_), a(a_) {
+        if (sizes) {
+            sz.assign(sizes, sizes + n);
+            b = *std::max_element(sz.begin(), sz.end());
+        }
+        od.assign(n + 1, 0);
+        oul.assign(n + 1, 0);
+        oar.assign(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            const size_t bi = bsz(i), bj = i + 1 < n ? bsz(i + 1) : 0;
+            od[i + 1] = od[i] + bi * bi;
+            oul[i + 1] = oul[i] + bi * bj;
+            oar[i + 1] = oar[i] + bi * (size_t)a;
+        }
+    }
+    int bsz(int i) const { return sz.empty() ? b : sz[i]; }
+    int dim(int u) const { return u == n ? a : bsz(u); }
+    bool uneven() const {
+        for (int v : sz)
+            if (v != sz[0]) return true;
+        return false;
+    }
 };
 
 // Elimination plan (host logic only).
@@ -183,10 +211,58 @@ bool validate_bounds(const Dims& D, const std::vector<int>& bounds, std::string&
     return true;
 }
 
+// Bounds for blocks of different sizes: the smallest largest-partition cost
+// (sum of F_k over the blocks a partition eliminates) found by bisection, each
+// trial assigning partitions left to right as far as the trial cost allows.
+std::vector<int> auto_bounds_uneven(const Dims& D, int P) {
+    const int n = D.n;
+    const double a = D.a;
+    auto F = [](double b, double Dn) { return 3 * b * b * b + 11 * Dn * b * b + 10 * Dn * Dn * b; };
+    auto bs = [&](int i) { return (double)D.bsz(i); };
+    auto last_cost = [&](int s) {
+        double c = 0;
+        for (int k = s + 1; k < n; ++k) c += F(bs(k), bs(k - 1) + a);
+        return c;
+    };
+    auto trial = [&](double T, std::vector<int>& out) {
+        out.assign(1, 0);
+        int s = 0;
+        for (int p = 0; p < P - 1; ++p) {
+            const int need_after = 2 * (P - 2 - p) + 1;   // blocks the later partitions need
+            const int minsz = p == 0 ? 1 : 2;
+            int e = s + minsz - 1;                        // last block of this partition
+            if (e > n - 1 - need_after) return false;
+            double c = 0;
+            while (e + 1 <= n - 1 - need_after) {
+                const double inc = p == 0 ? F(bs(e), bs(e + 1) + a) : F(bs(e), bs(s) + bs(e + 1) + a);
+                if (c + inc > T) break;
+                c += inc;
+                ++e;
+            }
+            out.push_back(e + 1);
+            s = e + 1;
+        }
+        out.push_back(n);
+        return last_cost(s) <= T;
+    };
+    double hi = 0;
+    for (int k = 0; k < n; ++k) hi += F(bs(k), 2 * D.b + a);
+    double lo = 0;
+    std::vector<int> best, cur;
+    if (!trial(hi, best)) return {};
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (trial(mid, cur)) { hi = mid; best = cur; }
+        else lo = mid;
+    }
+    return best;
+}
+
 // Balance F_k = 8(3b^3 + 11 D b^2 + 10 D^2 b) per partition, D = size of N(k).
 std::vector<int> auto_bounds(const Dims& D, int P) {
     std::vector<int> bounds;
     if (P <= 1) return {0, D.n};
+    if (D.uneven()) return auto_bounds_uneven(D, P);
     const double b = D.b, a = D.a;
     auto F = [&](double Dn) { return 3 * b * b * b + 11 * Dn * b * b + 10 * Dn * Dn * b; };
     const double fe = F(b + a), fm = F(2 * b + a);
@@ -253,18 +329,17 @@ struct Builder {
     // Caller block of field f for pair (u, v), or a fake unique address when
     // the caller pointer is null (dry runs only).
     MatRef ext_block(const bt_blocks& blk, int which, int u, int v) {
-        const int n = D.n, b = D.b, a = D.a, t = D.n;
+        const int t = D.n;
         void* base = nullptr;
         size_t offe = 0;
         int r = D.dim(u), c = D.dim(v);
         int field;
         if (u == t && v == t) { field = 5; base = blk.tip; offe = 0; }
-        else if (v == t) { field = 3; base = blk.arrow_right; offe = (size_t)u * b * a; }
-        else if (u == t) { field = 4; base = blk.arrow_bottom; offe = (size_t)v * a * b; }
-        else if (u == v) { field = 0; base = blk.diag; offe = (size_t)u * b * b; }
-        else if (v == u + 1) { field = 1; base = blk.upper; offe = (size_t)u * b * b; }
-        else { field = 2; base = blk.lower; offe = (size_t)v * b * b; }
-        (void)n;
+        else if (v == t) { field = 3; base = blk.arrow_right; offe = D.oar[u]; }
+        else if (u == t) { field = 4; base = blk.arrow_bottom; offe = D.oar[v]; }
+        else if (u == v) { field = 0; base = blk.diag; offe = D.od[u]; }
+        else if (v == u + 1) { field = 1; base = blk.upper; offe = D.oul[u]; }
+        else { field = 2; base = blk.lower; offe = D.oul[v]; }
         double2* p;
         if (base) p = reinterpret_cast<double2*>(base) + offe;
         else p = reinterpret_cast<double2*>((uintptr_t)(((uint64_t)(which * 8 + field + 1)) << 44)) + offe;
@@ -1160,9 +1235,22 @@ bt_status hip_err(bt_si_sq_plan* h, hipError_t e, const char* where) {
 
 bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
     if (!d) { msg = "null descriptor"; return false; }
-    if (d->n < 1 || d->b < 1 || d->a < 0) { msg = "need n >= 1, b >= 1, a >= 0"; return false; }
-    if (d->b > kInvMaxDim || d->a > kInvMaxDim) { msg = "block sizes above 1024 are not supported"; return false; }
+    if (d->n < 1 || d->a < 0) { msg = "need n >= 1, a >= 0"; return false; }
     if (d->n > 65535) { msg = "n above 65535 is not supported"; return false; }
+    if (d->block_sizes) {
+        for (int i = 0; i < d->n; ++i)
+            if (d->block_sizes[i] < 1 || d->block_sizes[i] > kInvMaxDim) {
+                msg = "block_sizes[" + std::to_string(i) + "] must lie in 1..1024";
+                return false;
+            }
+    } else if (d->b < 1) {
+        msg = "need b >= 1";
+        return false;
+    }
+    if ((!d->block_sizes && d->b > kInvMaxDim) || d->a > kInvMaxDim) {
+        msg = "block sizes above 1024 are not supported";
+        return false;
+    }
     if (d->precision != BT_FP64 && d->precision != BT_MIXED) { msg = "unknown precision"; return false; }
     if ((d->flags & BT_DIAG_ONLY) && d->precision == BT_MIXED) {
         msg = "BT_DIAG_ONLY needs BT_FP64: the mixed path's error estimate reads the off-diagonal blocks";
@@ -1170,7 +1258,7 @@ bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
     }
     const int P = d->partitions;
     if (P < 1) { msg = "partitions must be >= 1"; return false; }
-    Dims D{d->n, d->b, d->a};
+    Dims D(d->n, d->b, d->a, d->block_sizes);
     if (d->part_bounds) {
         bounds.assign(d->part_bounds, d->part_bounds + P + 1);
     } else {
@@ -1603,9 +1691,10 @@ bt_status plan_instances(int count, const bt_desc* descs, std::vector<Instance>&
             if (count > 1) msg = "instance " + std::to_string(i) + ": " + msg;
             return set_err(nullptr, BT_ERR_INVALID, msg);
         }
-        inst[i].D = Dims{descs[i].n, descs[i].b, descs[i].a};
+        inst[i].D = Dims(descs[i].n, descs[i].b, descs[i].a, descs[i].block_sizes);
         inst[i].desc = descs[i];
         inst[i].desc.part_bounds = nullptr;
+        inst[i].desc.block_sizes = nullptr;   // the sizes live in inst[i].D
         if (!(inst[i].desc.tol > 0)) inst[i].desc.tol = 1e-4;
         inst[i].bounds = bounds;
     }
@@ -2144,7 +2233,7 @@ extern "C" size_t bt_si_sq_diag_schedule(const bt_desc* desc, char* out, size_t 
     std::string msg;
     if (!desc_bounds(desc, bounds, msg)) { g_last_error = msg; return 0; }
     Builder bd;
-    bd.D = Dims{desc->n, desc->b, desc->a};
+    bd.D = Dims(desc->n, desc->b, desc->a, desc->block_sizes);
     bd.bounds = bounds;
     bd.mode = MODE_BOTH;
     bd.mixed_bulk = desc->precision == BT_MIXED;

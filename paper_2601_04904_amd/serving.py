@@ -142,7 +142,7 @@ class PrecisionRouter:
 
 class ServingEngine:
     def __init__(self, budget_bytes: int, max_inflight: int = 2, max_wave: int = 16,
-                 input_fn=None, router: PrecisionRouter | None = None):
+                 input_fn=None, router: PrecisionRouter | None = None, log=None):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -164,6 +164,7 @@ class ServingEngine:
         self.release_above = 8 << 30      # cached-but-unused torch memory released before a wave
         self.size_ratio = 8.0             # largest work ratio between requests of one wave
         self.threads = []
+        self.log = log                    # callable taking a progress line (one per finished wave)
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -261,7 +262,11 @@ class ServingEngine:
                     self.used -= r.footprint
                     self.done.append(r)
                 self.busy -= 1
+                ndone = len(self.done)
                 self.cv.notify_all()
+            if self.log is not None:
+                self.log(f"[serve] wave of {len(wave)} finished at {self.now():.2f} s "
+                         f"({ndone} requests done)")
 
     def _batch_solver(self, specs, stream):
         """The library allocates its workspace outside torch's caching allocator,
@@ -340,10 +345,20 @@ def summarize(done, wall):
                 fallbacks=sum(any(r.fallback) for r in done))
 
 
+def auto_partitions(n: int) -> int:
+    """Partitions for a served request: two (the first half eliminated
+    top-down, the second bottom-up, Sec. III-B with P = 2) halve the
+    sequential chain of block inverses at almost no extra work (no middle
+    partitions, no fill-in); very short chains stay sequential."""
+    return 2 if n >= 8 else 1
+
+
 def requests_from_trace(trace, partitions=1):
+    """Requests of a trace; partitions is a count or a function of n."""
     out = []
     for k, t in enumerate(trace):
+        P = partitions(t["n"]) if callable(partitions) else partitions
         out.append(Request(rid=k, n=t["n"], b=t["b"], a=t["a"], precision=t["precision"], E=t["E"],
                            eta=t["eta"], seed=t["seed"], nrhs=t["nrhs"], arrival=t["arrival"],
-                           partitions=partitions))
+                           partitions=P))
     return out

@@ -72,21 +72,97 @@ class DeviceBlocks:
         return bl
 
 
-def workspace_bytes(n, b, a=0, partitions=1, bounds=None, precision=BT_FP64) -> int:
-    d = make_desc(n, b, a, partitions, bounds, precision)
+class VarDeviceBlocks:
+    """Device storage for diagonal blocks of different sizes, in the layout of
+    include/bt_si_sq.h: one flat complex128 tensor per field, block i of a
+    field after blocks 0..i-1 of that field."""
+
+    def __init__(self, sizes, a, diag, upper, lower, arrow_right, arrow_bottom, tip):
+        self.sizes, self.a = [int(v) for v in sizes], int(a)
+        self.diag, self.upper, self.lower = diag, upper, lower
+        self.arrow_right, self.arrow_bottom, self.tip = arrow_right, arrow_bottom, tip
+
+    @property
+    def n(self):
+        return len(self.sizes)
+
+    @staticmethod
+    def _counts(sizes, a):
+        n = len(sizes)
+        return dict(diag=[s * s for s in sizes],
+                    upper=[sizes[i] * sizes[i + 1] for i in range(n - 1)],
+                    lower=[sizes[i] * sizes[i + 1] for i in range(n - 1)],
+                    arrow_right=[s * a for s in sizes], arrow_bottom=[s * a for s in sizes],
+                    tip=[a * a])
+
+    @staticmethod
+    def empty(sizes, a, device="cuda", zero=False):
+        torch = _torch()
+        f = torch.zeros if zero else torch.empty
+        cnt = VarDeviceBlocks._counts(sizes, a)
+        return VarDeviceBlocks(sizes, a, *[f(sum(cnt[k]), dtype=torch.complex128, device=device)
+                                           for k in FIELDS])
+
+    @staticmethod
+    def from_host(M, device="cuda"):
+        """From any object with list-of-blocks fields (synth.VBTA)."""
+        torch = _torch()
+        sizes = [int(np.shape(d)[0]) for d in M.diag]
+        a = int(np.shape(M.tip)[0])
+        flat = []
+        for k in FIELDS:
+            v = getattr(M, k)
+            parts = [np.asarray(v, dtype=np.complex128).ravel()] if k == "tip" else \
+                [np.asarray(x, dtype=np.complex128).ravel() for x in v]
+            arr = np.concatenate(parts) if parts else np.zeros(0, np.complex128)
+            flat.append(torch.from_numpy(np.ascontiguousarray(arr)).to(device))
+        return VarDeviceBlocks(sizes, a, *flat)
+
+    def to_host(self):
+        """Lists of blocks (tip as one array)."""
+        from types import SimpleNamespace
+        n, sz, a = self.n, self.sizes, self.a
+        shapes = dict(diag=[(s, s) for s in sz],
+                      upper=[(sz[i], sz[i + 1]) for i in range(n - 1)],
+                      lower=[(sz[i + 1], sz[i]) for i in range(n - 1)],
+                      arrow_right=[(s, a) for s in sz], arrow_bottom=[(a, s) for s in sz])
+        out = {}
+        for k in FIELDS:
+            flat = getattr(self, k).cpu().numpy()
+            if k == "tip":
+                out[k] = flat.reshape(a, a)
+                continue
+            blocks, off = [], 0
+            for r, c in shapes[k]:
+                blocks.append(flat[off:off + r * c].reshape(r, c))
+                off += r * c
+            out[k] = blocks
+        return SimpleNamespace(**out)
+
+    def c_blocks(self) -> _lib.bt_blocks:
+        bl = _lib.bt_blocks()
+        for f in FIELDS:
+            t = getattr(self, f)
+            assert t.is_contiguous() and t.dtype.is_complex
+            setattr(bl, f, t.data_ptr() if t.numel() > 0 else None)
+        return bl
+
+
+def workspace_bytes(n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, sizes=None) -> int:
+    d = make_desc(n, b, a, partitions, bounds, precision, sizes=sizes)
     return int(_lib.lib().bt_si_sq_workspace_bytes(C.byref(d)))
 
 
-def partition_bounds(n, b, a=0, partitions=1, bounds=None):
-    d = make_desc(n, b, a, partitions, bounds)
+def partition_bounds(n, b, a=0, partitions=1, bounds=None, sizes=None):
+    d = make_desc(n, b, a, partitions, bounds, sizes=sizes)
     out = (C.c_int32 * (partitions + 1))()
     check(_lib.lib().bt_si_sq_partition_bounds(C.byref(d), out))
     return list(out)
 
 
-def flops(n, b, a=0, partitions=1, bounds=None, flags=0):
+def flops(n, b, a=0, partitions=1, bounds=None, flags=0, sizes=None):
     """(executed, useful) real flops of one fused SI+SQ solve."""
-    d = make_desc(n, b, a, partitions, bounds, flags=flags)
+    d = make_desc(n, b, a, partitions, bounds, flags=flags, sizes=sizes)
     ex, us = C.c_double(), C.c_double()
     check(_lib.lib().bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)))
     return ex.value, us.value
@@ -101,10 +177,10 @@ class Solver:
     """
 
     def __init__(self, n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, tol=1e-4,
-                 stream=None, flags=0):
+                 stream=None, flags=0, sizes=None):
         torch = _torch()
         self.n, self.b, self.a = n, b, a
-        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol, flags)
+        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol, flags, sizes)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         check(_lib.lib().bt_si_sq_create(C.byref(self._desc), C.c_void_p(self.stream.cuda_stream),
@@ -179,9 +255,9 @@ class BatchSolver:
     def __init__(self, specs, stream=None):
         torch = _torch()
         self.count = len(specs)
-        self._descs = [make_desc(sp["n"], sp["b"], sp.get("a", 0), sp.get("partitions", 1),
+        self._descs = [make_desc(sp["n"], sp.get("b", 0), sp.get("a", 0), sp.get("partitions", 1),
                                  sp.get("bounds"), sp.get("precision", BT_FP64), sp.get("tol", 1e-4),
-                                 sp.get("flags", 0))
+                                 sp.get("flags", 0), sp.get("sizes"))
                        for sp in specs]
         arr = (_lib.bt_desc * self.count)(*self._descs)
         self._arr = arr
@@ -239,13 +315,14 @@ class BatchSolver:
 
 
 def batch_workspace_bytes(specs) -> int:
-    descs = [make_desc(sp["n"], sp["b"], sp.get("a", 0), sp.get("partitions", 1), sp.get("bounds"),
-                       sp.get("precision", BT_FP64), sp.get("tol", 1e-4)) for sp in specs]
+    descs = [make_desc(sp["n"], sp.get("b", 0), sp.get("a", 0), sp.get("partitions", 1), sp.get("bounds"),
+                       sp.get("precision", BT_FP64), sp.get("tol", 1e-4), sp.get("flags", 0),
+                       sp.get("sizes")) for sp in specs]
     arr = (_lib.bt_desc * len(descs))(*descs)
     return int(_lib.lib().bt_si_sq_batch_workspace_bytes(len(descs), arr))
 
 
-__all__ = ["DeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
+__all__ = ["DeviceBlocks", "VarDeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
            "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN",
            "BT_DIAG_ONLY", "BTError", "BTToleranceError",
            "autotune", "tune_table", "set_tune_table"]

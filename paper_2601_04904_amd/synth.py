@@ -269,8 +269,14 @@ def perturb(M: BTA, rel: float, seed: int) -> BTA:
     measures how much that algorithm and input amplify rounding.  Pure input
     construction."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    out = M.copy()
-    for f in out.fields():
+    if isinstance(M, VBTA):
+        out = VBTA(*([np.array(x, copy=True) for x in f] if isinstance(f, list) else np.array(f, copy=True)
+                     for f in M.fields()))
+        pieces = [x for f in out.fields() for x in (f if isinstance(f, list) else [f])]
+    else:
+        out = M.copy()
+        pieces = list(out.fields())
+    for f in pieces:
         if f.size:
             u = rng.uniform(-1.0, 1.0, f.shape) + 1j * rng.uniform(-1.0, 1.0, f.shape)
             f *= 1.0 + rel * u

@@ -23,6 +23,8 @@ Calls only the oracle and the seeded input generators.
 
     python tests/golden/make_fullsize_floors.py bt_n64_b512          (about 5 min on 8 cores)
     python tests/golden/make_fullsize_floors.py bta_n128_b384_a512   (about 10 min)
+    python tests/golden/make_fullsize_floors.py vb_n48_b256to512     (about 2 min; blocks of
+    python tests/golden/make_fullsize_floors.py vbta_n48_b256to512_a256   different sizes)
 """
 import json
 import os
@@ -36,19 +38,24 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 from oracle.partitioned import _forward_partitions  # noqa: E402
-from paper_2601_04904_amd.synth import BTA, CONFIGS, config_problem, perturb  # noqa: E402
+from paper_2601_04904_amd.synth import BTA, CONFIGS, VAR_CONFIGS, VBTA, config_problem, perturb  # noqa: E402
 from tests._util import rel_err  # noqa: E402
 
 # the library's default partition bounds for these sizes (pinned by the ABI tests)
 FORMS = {
     "bt_n64_b512": {2: [0, 32, 64], 8: [0, 14, 20, 26, 32, 38, 44, 50, 64]},
     "bta_n128_b384_a512": {2: [0, 64, 128], 16: list(range(0, 129, 8))},
+    "vb_n48_b256to512": {4: [0, 17, 24, 31, 48]},
+    "vbta_n48_b256to512_a256": {4: [0, 16, 24, 32, 48]},
 }
 REL = 2.0 ** -53        # perturbation: one unit roundoff
 
 
 def reverse(M):
     """J M J for a block matrix: block i -> n-1-i (upper and lower swap)."""
+    if isinstance(M.diag, list):
+        return VBTA(M.diag[::-1], M.lower[::-1], M.upper[::-1], M.arrow_right[::-1],
+                    M.arrow_bottom[::-1], np.array(M.tip))
     return BTA(M.diag[::-1].copy(), M.lower[::-1].copy(), M.upper[::-1].copy(),
                M.arrow_right[::-1].copy(), M.arrow_bottom[::-1].copy(), np.array(M.tip))
 
@@ -70,7 +77,7 @@ def blk(M, i, j, n):
 def residuals(A, B, XR, XL):
     """Max over block rows of ||sum_j A_ij X^R_ji - I|| / sum_j ||A_ij|| ||X^R_ji|| and of
     ||sum_j A_ij X^<_ji - sum_j B_ij (X^R_ij)^H|| / (the matching sum of norms)."""
-    n, a = A.diag.shape[0], A.tip.shape[0]
+    n, a = len(A.diag), A.tip.shape[0]
     rows = n + (1 if a > 0 else 0)
     wr = wl = 0.0
     for i in range(rows):
@@ -95,7 +102,7 @@ def sequential(A, B):
 
 
 def conditioning(A, B, bounds_by_P):
-    n = A.diag.shape[0]
+    n = len(A.diag)
     dom = []
     for i in range(n):
         off = (np.linalg.norm(A.lower[i - 1], 2) if i > 0 else 0.0) + \
@@ -117,11 +124,14 @@ def conditioning(A, B, bounds_by_P):
 
 def main():
     name = sys.argv[1]
-    cfg = CONFIGS[name]
+    if name in VAR_CONFIGS:
+        E, eta = VAR_CONFIGS[name]["E"], VAR_CONFIGS[name]["eta"]
+    else:
+        E, eta = CONFIGS[name].E, CONFIGS[name].eta
     A, B = config_problem(name)
     Ap, Bp = perturb(A, REL, 1), perturb(B, REL, 2)
     t0 = time.perf_counter()
-    out = {"workload": name, "E": cfg.E, "eta": cfg.eta,
+    out = {"workload": name, "E": E, "eta": eta,
            "metric": "max over selected blocks of ||X1 - X2||_F / max(||X2||_F, 1e-6 max_j ||X2_j||_F)",
            "perturbation": "entries x (1 + 2^-53 u), u uniform in [-1,1] + i[-1,1], seeds 1 (A) and 2 (B)",
            "forms": {}}

@@ -35,10 +35,29 @@ def test_library_exports_every_declared_symbol():
     assert set(_lib.EXPORTED) == declared_functions()
 
 
-def test_struct_layout_matches_header():
-    # int32 n, b, a, partitions; pointer; int32 precision; double tol; uint32 flags
-    assert C.sizeof(_lib.bt_desc) == 48
-    assert C.sizeof(_lib.bt_blocks) == 6 * 8
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes structs have the size and field offsets the C compiler gives
+    the header's structs (a small C program built against include/)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in _lib.bt_desc._fields_]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bt_si_sq.h"', "int main(void) {",
+             '  printf("%zu\\n", sizeof(bt_desc));']
+    lines += [f'  printf("%zu\\n", offsetof(bt_desc, {f}));' for f in fields]
+    lines += ['  printf("%zu\\n", sizeof(bt_blocks));', "  return 0; }"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                           text=True).stdout.split()]
+    assert vals[0] == C.sizeof(_lib.bt_desc)
+    assert vals[1:1 + len(fields)] == [getattr(_lib.bt_desc, f).offset for f in fields]
+    assert vals[-1] == C.sizeof(_lib.bt_blocks) == 6 * 8
 
 
 def _bounds(n, b, a, P, bounds=None):
@@ -258,3 +277,52 @@ def test_diag_only_flop_model_and_mixed_rejection():
     d = LB.make_desc(8, 16, 0, 1, None, precision=LB.BT_MIXED, flags=LB.BT_DIAG_ONLY)
     assert L.bt_si_sq_workspace_bytes(C.byref(d)) == 0
     assert b"BT_DIAG_ONLY" in L.bt_si_sq_last_error(None)
+
+
+def test_block_sizes_descriptor():
+    """Per-block sizes (Sec. II-A): the executed flops of the sequential sweep
+    equal sum_k 8(3 b_k^3 + 11 D_k b_k^2 + 10 D_k^2 b_k) with D_k the total size
+    of block k's remaining neighbours; equal sizes give the uniform results;
+    cost-model bounds are admissible; bad sizes are refused."""
+    import random
+    from paper_2601_04904_amd import _lib as LB
+    L = _lib.lib()
+    rng = random.Random(11)
+    for _ in range(5):
+        n = rng.randint(2, 12)
+        sizes = [rng.randint(1, 40) for _ in range(n)]
+        a = rng.choice([0, 7])
+        d = LB.make_desc(n, 0, a, 1, None, sizes=sizes)
+        ex, us = C.c_double(), C.c_double()
+        assert L.bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)) == BT_OK
+        want = 0.0
+        for k in range(n):
+            Dk = (sizes[k + 1] if k + 1 < n else 0) + a
+            b = sizes[k]
+            want += 8.0 * (3 * b ** 3 + 11 * Dk * b * b + 10 * Dk * Dk * b)
+        want += 8.0 * 3 * a ** 3
+        assert ex.value == want
+    # equal sizes: same flops, bounds and workspace as the uniform descriptor
+    for P in (1, 3):
+        du = make_desc(20, 64, 16, P)
+        dv = LB.make_desc(20, 0, 16, P, None, sizes=[64] * 20)
+        assert L.bt_si_sq_workspace_bytes(C.byref(du)) == L.bt_si_sq_workspace_bytes(C.byref(dv))
+        bu, bv = (C.c_int32 * (P + 1))(), (C.c_int32 * (P + 1))()
+        assert L.bt_si_sq_partition_bounds(C.byref(du), bu) == BT_OK
+        assert L.bt_si_sq_partition_bounds(C.byref(dv), bv) == BT_OK
+        assert list(bu) == list(bv)
+    # uneven cost-model bounds: first/last partitions >= 1 block, middles >= 2
+    from paper_2601_04904_amd.synth import ramp_sizes
+    sz = ramp_sizes(48, 256, 512, 4)
+    for P in (2, 4, 8, 16):
+        d = LB.make_desc(48, 0, 256, P, None, sizes=sz)
+        out = (C.c_int32 * (P + 1))()
+        assert L.bt_si_sq_partition_bounds(C.byref(d), out) == BT_OK
+        bd = list(out)
+        assert bd[0] == 0 and bd[-1] == 48
+        parts = [bd[p + 1] - bd[p] for p in range(P)]
+        assert parts[0] >= 1 and parts[-1] >= 1 and all(x >= 2 for x in parts[1:-1])
+    for bad in ([4, 0, 4], [4, 1025, 4]):
+        d = LB.make_desc(3, 0, 0, 1, None, sizes=bad)
+        assert L.bt_si_sq_workspace_bytes(C.byref(d)) == 0
+        assert b"block_sizes" in L.bt_si_sq_last_error(None)
