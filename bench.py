@@ -269,7 +269,7 @@ def bench_serve(args, torch, S):
         stats["waves"] = eng.waves
         stats["errors"] = eng.errors
         stats["routed_to_fp64"] = eng.router.routed
-        stats["oom_retries"] = eng.oom_retries
+        stats["arena_misses"] = eng.arena_misses
         log(f"[bench] serving at {rate:g}/s: {stats}")
         # plain RGF on the same trace: FP64, sequential sweep, one request at a
         # time, one launch per single-term product, one stream
@@ -340,8 +340,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--serve-max-n", type=int, default=256)
     ap.add_argument("--serve-max-b", type=int, default=1024)
-    ap.add_argument("--serve-budget-gb", type=float, default=240.0)
-    ap.add_argument("--inflight", type=int, default=3)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--inflight", type=int, default=2)
     ap.add_argument("--max-wave", type=int, default=8)
     ap.add_argument("--antihermitian", type=int, default=1,
                     help="1: also time the reported form with BT_SIGMA_ANTIHERMITIAN (the synthetic "

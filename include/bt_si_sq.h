@@ -139,8 +139,9 @@ typedef struct {
     void* tip;
 } bt_blocks;
 
-/* Device bytes the handle for this descriptor allocates (workspace for the
- * stored factors, fill-in, reduced system and intermediates).  Pure host
+/* Device bytes the handle for this descriptor allocates (one block: workspace
+ * for the stored factors, fill-in, reduced system and intermediates, the
+ * inverse scratch, and room for the uploaded operation lists).  Pure host
  * computation, no side effects; 0 for an invalid descriptor.  Used for
  * admission by device-memory footprint. */
 size_t bt_si_sq_workspace_bytes(const bt_desc* desc);
@@ -209,6 +210,19 @@ size_t bt_si_sq_batch_workspace_bytes(int32_t count, const bt_desc* descs);
 
 bt_status bt_si_sq_batch_create(int32_t count, const bt_desc* descs, void* hip_stream,
                                 bt_si_sq_handle* out);
+
+/* bt_si_sq_batch_create with device memory the caller provides, for callers
+ * that keep a pool (a serving loop drawing on a caching allocator): the
+ * handle takes its workspace, inverse scratch, status word and the room for
+ * its uploaded operation lists from `workspace` (device memory of at least
+ * bt_si_sq_batch_workspace_bytes(count, descs) bytes, 256-byte aligned) and
+ * allocates no other device memory in normal operation (an operation list
+ * larger than that room, which no schedule of the library produces, gets an
+ * allocation of its own).  The caller owns `workspace`: it must stay
+ * allocated and untouched until bt_si_sq_destroy returns; destroy does not
+ * free it.  BT_ERR_INVALID for a null, misaligned or too small workspace. */
+bt_status bt_si_sq_batch_create_in(int32_t count, const bt_desc* descs, void* hip_stream,
+                                   void* workspace, size_t workspace_bytes, bt_si_sq_handle* out);
 
 /* A, B, XL: arrays of `count` bt_blocks (instance i uses element i); XR may be
  * NULL or have all-NULL elements (X^R then stays in the workspace).

@@ -23,7 +23,8 @@ EXPORTED = [
     "bt_si_sq_create", "bt_si_sq_factor", "bt_si_sq_selected_solve", "bt_si_sq_solve",
     "bt_si_sq_sync", "bt_si_sq_destroy", "bt_si_sq_last_error", "bt_si_sq_last_launch_count",
     "bt_si_sq_profile", "bt_si_sq_profile_stats",
-    "bt_si_sq_batch_workspace_bytes", "bt_si_sq_batch_create", "bt_si_sq_batch_solve",
+    "bt_si_sq_batch_workspace_bytes", "bt_si_sq_batch_create", "bt_si_sq_batch_create_in",
+    "bt_si_sq_batch_solve",
     "bt_si_sq_batch_count", "bt_si_sq_batch_selected_solve",
     "bt_si_sq_autotune", "bt_si_sq_tune_table",
     "bt_si_sq_diag_gemm", "bt_si_sq_diag_inverse", "bt_si_sq_diag_schedule",
@@ -114,6 +115,9 @@ def lib():
     L.bt_si_sq_batch_workspace_bytes.restype = C.c_size_t
     L.bt_si_sq_batch_create.argtypes = [C.c_int32, C.POINTER(bt_desc), C.c_void_p, C.POINTER(H)]
     L.bt_si_sq_batch_create.restype = C.c_int
+    L.bt_si_sq_batch_create_in.argtypes = [C.c_int32, C.POINTER(bt_desc), C.c_void_p, C.c_void_p,
+                                           C.c_size_t, C.POINTER(H)]
+    L.bt_si_sq_batch_create_in.restype = C.c_int
     L.bt_si_sq_batch_solve.argtypes = [H, C.POINTER(bt_blocks), C.POINTER(bt_blocks),
                                        C.POINTER(bt_blocks), C.POINTER(bt_blocks),
                                        C.POINTER(C.c_double), C.POINTER(C.c_int)]

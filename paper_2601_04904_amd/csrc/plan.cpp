@@ -1181,11 +1181,18 @@ struct bt_si_sq_plan {
     hipStream_t stream = nullptr;     // the caller's stream (main stream)
     hipStream_t astream = nullptr;    // internal stream for the critical A-chain
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    // All device memory of the handle is one block: [workspace | inverse
+    // scratch | status word | arena for the uploaded operation lists], either
+    // allocated at create (own_block) or given by the caller.
+    char* block = nullptr;
+    bool own_block = true;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* inv_pool = nullptr;
     size_t inv_bytes = 0;
     DevStatus* status = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
     std::string err;
     int32_t last_launches = 0;
     bool use_graph = false;               // BT_GRAPH on every instance
@@ -1199,14 +1206,14 @@ struct bt_si_sq_plan {
         std::vector<int> sel;             // instances of this program
         char* dev = nullptr;
         size_t dev_bytes = 0;
+        bool dev_own = false;             // dev allocated on its own (did not fit the arena)
+        std::vector<char> host;           // host copy the upload reads (kept as long as dev)
         size_t off_gemm = 0, off_inv = 0, off_add = 0, off_norm = 0;
         std::vector<hipEvent_t> events;   // cross-stream events of the launch list
         hipGraphExec_t graph = nullptr;   // the launch list captured as a graph (BT_GRAPH)
     };
     std::vector<Cached> cache;            // small LRU of compiled programs
     uint64_t clock = 0;
-    char* host_stage = nullptr;
-    size_t host_stage_bytes = 0;
     hipEvent_t upload_done = nullptr;
     // profiling
     bool profiling = false;
@@ -1463,12 +1470,42 @@ std::vector<uint64_t> make_key(Mode mode, bool fp64_rerun, const std::vector<int
     return k;
 }
 
+// Device bytes of a compiled program's operation lists (each array starting
+// on a 256-byte boundary, as prepare_and_run lays them out).
+size_t program_bytes(const Program& pg) {
+    const size_t bg = pg.gemm.size() * sizeof(GemmOp);
+    const size_t bi = pg.inv.size() * sizeof(InvJob);
+    const size_t ba = pg.add.size() * sizeof(AddOp);
+    const size_t bn = pg.norm.size() * sizeof(NormJob);
+    return align256(align256(align256(bg) + bi) + ba) + bn + 256;
+}
+
+// Layout of a handle's device block (see bt_si_sq_plan): workspace, inverse
+// scratch, status word, then room for kArenaPrograms operation lists the size
+// of the fused solve's (the largest a handle compiles: selected solves and
+// factors take subsets of it, FP64 re-runs the same).
+constexpr size_t kArenaPrograms = 4;
+struct BlockLayout {
+    size_t inv_off, status_off, arena_off, arena_bytes, total;
+};
+BlockLayout block_layout(size_t ws_bytes, size_t inv_bytes, size_t prog_bytes) {
+    BlockLayout L;
+    L.inv_off = align256(ws_bytes);
+    L.status_off = L.inv_off + align256(std::max<size_t>(inv_bytes, 256));
+    L.arena_off = L.status_off + 256;
+    L.arena_bytes = kArenaPrograms * align256(prog_bytes);
+    L.total = L.arena_off + L.arena_bytes;
+    return L;
+}
+
 void free_cached(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c) {
     if (c.dev) {
+        // the launch list's kernels may still read it on either stream
         hipStreamSynchronize(h->stream);
         hipStreamSynchronize(h->astream);
-        hipFree(c.dev);
+        if (c.dev_own) hipFree(c.dev);
         c.dev = nullptr;
+        c.dev_own = false;
     }
     if (c.graph) {
         hipStreamSynchronize(h->stream);
@@ -1508,6 +1545,16 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& s
         const size_t off_add = (off_inv + bi + 255) & ~(size_t)255;
         const size_t off_norm = (off_add + ba + 255) & ~(size_t)255;
         const size_t total = off_norm + bn + 256;
+        // Device room for the lists: the handle's arena, taken in order; when
+        // it is full every cached program is dropped (after its streams are
+        // idle) and the arena starts over.  A list larger than the whole
+        // arena gets an allocation of its own.
+        const size_t need = align256(total);
+        if (h->arena_used + need > h->arena_bytes && need <= h->arena_bytes) {
+            for (auto& x : h->cache) free_cached(h, x);
+            h->cache.clear();
+            h->arena_used = 0;
+        }
         // slot: a free one, else the least recently used
         if (h->cache.size() < kMaxCached) {
             h->cache.emplace_back();
@@ -1520,23 +1567,24 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& s
             c->key.clear();
             c->dev_bytes = 0;
         }
-        // the previous upload must have left the staging buffer
-        if (h->upload_done) hipEventSynchronize(h->upload_done);
-        hipError_t e = hipMalloc(&c->dev, total);
-        if (e != hipSuccess) { c->dev = nullptr; return set_err(h, BT_ERR_OOM, "operation list allocation failed"); }
-        c->dev_bytes = total;
-        if (total > h->host_stage_bytes) {
-            if (h->host_stage) hipHostFree(h->host_stage);
-            h->host_stage = nullptr;
-            e = hipHostMalloc((void**)&h->host_stage, total, 0);
-            if (e != hipSuccess) { h->host_stage_bytes = 0; return hip_err(h, e, "hipHostMalloc"); }
-            h->host_stage_bytes = total;
+        hipError_t e = hipSuccess;
+        if (h->arena_used + need <= h->arena_bytes) {
+            c->dev = h->arena + h->arena_used;
+            h->arena_used += need;
+            c->dev_own = false;
+        } else {
+            e = hipMalloc(&c->dev, total);
+            if (e != hipSuccess) { c->dev = nullptr; return set_err(h, BT_ERR_OOM, "operation list allocation failed"); }
+            c->dev_own = true;
         }
-        if (bg) memcpy(h->host_stage, pg.gemm.data(), bg);
-        if (bi) memcpy(h->host_stage + off_inv, pg.inv.data(), bi);
-        if (ba) memcpy(h->host_stage + off_add, pg.add.data(), ba);
-        if (bn) memcpy(h->host_stage + off_norm, pg.norm.data(), bn);
-        e = hipMemcpyAsync(c->dev, h->host_stage, total, hipMemcpyHostToDevice, h->stream);
+        c->dev_bytes = total;
+        c->host.assign(total, 0);
+        char* stage = c->host.data();
+        if (bg) memcpy(stage, pg.gemm.data(), bg);
+        if (bi) memcpy(stage + off_inv, pg.inv.data(), bi);
+        if (ba) memcpy(stage + off_add, pg.add.data(), ba);
+        if (bn) memcpy(stage + off_norm, pg.norm.data(), bn);
+        e = hipMemcpyAsync(c->dev, stage, total, hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) return hip_err(h, e, "hipMemcpyAsync(op list)");
         e = hipEventRecord(h->upload_done, h->stream);
         if (e != hipSuccess) return hip_err(h, e, "hipEventRecord");
@@ -1577,7 +1625,8 @@ bt_status read_estimates(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, std::vector
         const Instance& I = h->inst[c.sel[q]];
         const int rows = I.D.n + (I.D.a > 0 ? 1 : 0);
         std::vector<double> v(5 * (I.D.n + 1), 0.0);
-        e = hipMemcpy(v.data(), c.norm_out[q], v.size() * sizeof(double), hipMemcpyDeviceToHost);
+        e = hipMemcpyAsync(v.data(), c.norm_out[q], v.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_err(h, e, "residual readback");
         double nA = 0, nG = 0, nL = 0, rR = 0, rL = 0;
         for (int i = 0; i < rows; ++i) {
@@ -1681,7 +1730,7 @@ bool diag_only_of(const Instance& I) { return (I.desc.flags & BT_DIAG_ONLY) != 0
 
 // Validate descriptors and size the workspace of a batch (dry run).
 bt_status plan_instances(int count, const bt_desc* descs, std::vector<Instance>& inst,
-                         size_t& ws_bytes, size_t& inv_bytes, double* flops) {
+                         size_t& ws_bytes, size_t& inv_bytes, double* flops, size_t* prog_bytes = nullptr) {
     if (count < 1 || !descs) return set_err(nullptr, BT_ERR_INVALID, "need count >= 1 descriptors");
     inst.assign(count, Instance{});
     std::string msg;
@@ -1711,35 +1760,63 @@ bt_status plan_instances(int count, const bt_desc* descs, std::vector<Instance>&
     Program pg = compile(bt.ops, nl, reinterpret_cast<char*>((uintptr_t)3 << 40));
     if (!pg.error.empty()) return set_err(nullptr, BT_ERR_INVALID, pg.error);
     inv_bytes = pg.inv_scratch_bytes;
+    if (prog_bytes) *prog_bytes = program_bytes(pg);
     return BT_OK;
 }
 
-bt_status create_handle(int count, const bt_desc* descs, void* hip_stream, bt_si_sq_handle* out) {
+// ext: the caller's device block (ext_bytes at least the layout's total), or
+// null to allocate it here.
+bt_status create_handle(int count, const bt_desc* descs, void* hip_stream, bt_si_sq_handle* out,
+                        void* ext = nullptr, size_t ext_bytes = 0) {
     if (!out) return set_err(nullptr, BT_ERR_INVALID, "out is null");
     *out = nullptr;
     std::unique_ptr<bt_si_sq_plan> h(new bt_si_sq_plan());
-    bt_status st = plan_instances(count, descs, h->inst, h->ws_bytes, h->inv_bytes, nullptr);
+    size_t prog = 0;
+    bt_status st = plan_instances(count, descs, h->inst, h->ws_bytes, h->inv_bytes, nullptr, &prog);
     if (st != BT_OK) return st;
+    const BlockLayout L = block_layout(h->ws_bytes, h->inv_bytes, prog);
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    hipError_t e = hipMalloc(&h->ws, h->ws_bytes);
-    if (e != hipSuccess) { hipGetLastError(); return set_err(nullptr, BT_ERR_OOM, "workspace allocation failed"); }
-    e = hipMalloc(&h->inv_pool, std::max<size_t>(h->inv_bytes, 256));
-    if (e != hipSuccess) { hipGetLastError(); hipFree(h->ws); return set_err(nullptr, BT_ERR_OOM, "inverse scratch allocation failed"); }
-    e = hipMalloc(&h->status, sizeof(DevStatus));
-    if (e != hipSuccess) { hipFree(h->ws); hipFree(h->inv_pool); return set_err(nullptr, BT_ERR_OOM, "status allocation failed"); }
+    hipError_t e = hipSuccess;
+    if (ext) {
+        if (ext_bytes < L.total)
+            return set_err(nullptr, BT_ERR_INVALID, "workspace of " + std::to_string(ext_bytes) +
+                           " bytes is smaller than the " + std::to_string(L.total) + " this handle needs");
+        if (reinterpret_cast<uintptr_t>(ext) & 255)
+            return set_err(nullptr, BT_ERR_INVALID, "workspace must be 256-byte aligned");
+        h->block = static_cast<char*>(ext);
+        h->own_block = false;
+    } else {
+        e = hipMalloc(&h->block, L.total);
+        if (e != hipSuccess) { hipGetLastError(); return set_err(nullptr, BT_ERR_OOM, "workspace allocation failed"); }
+        h->own_block = true;
+    }
+    h->ws = h->block;
+    h->inv_pool = h->block + L.inv_off;
+    h->status = reinterpret_cast<DevStatus*>(h->block + L.status_off);
+    h->arena = h->block + L.arena_off;
+    h->arena_bytes = L.arena_bytes;
+    h->arena_used = 0;
+    // status word and the identity blocks of the residual check (each
+    // instance's first two slots), ordered on the handle's stream only
+    std::vector<double2> host;
     DevStatus z{0, 0};
-    e = hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
-    // identity blocks used by the residual check: each instance's first two slots
+    e = hipMemcpyAsync(h->status, &z, sizeof z, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     for (auto& I : h->inst) {
         if (e != hipSuccess) break;
         const int b = I.D.b, a = std::max(I.D.a, 1);
-        std::vector<double2> Ib((size_t)b * b, cplx(0));
-        for (int i = 0; i < b; ++i) Ib[(size_t)i * b + i] = cplx(1);
-        e = hipMemcpy(h->ws + I.ws_begin, Ib.data(), Ib.size() * sizeof(double2), hipMemcpyHostToDevice);
+        host.assign((size_t)b * b, cplx(0));
+        for (int i = 0; i < b; ++i) host[(size_t)i * b + i] = cplx(1);
+        e = hipMemcpyAsync(h->ws + I.ws_begin, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice,
+                           h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         const size_t offa = I.ws_begin + (((size_t)b * b * sizeof(double2) + 255) & ~(size_t)255);
-        std::vector<double2> Ia((size_t)a * a, cplx(0));
-        for (int i = 0; i < a; ++i) Ia[(size_t)i * a + i] = cplx(1);
-        if (e == hipSuccess) e = hipMemcpy(h->ws + offa, Ia.data(), Ia.size() * sizeof(double2), hipMemcpyHostToDevice);
+        host.assign((size_t)a * a, cplx(0));
+        for (int i = 0; i < a; ++i) host[(size_t)i * a + i] = cplx(1);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->ws + offa, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice,
+                               h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->upload_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming);
@@ -1751,7 +1828,7 @@ bt_status create_handle(int count, const bt_desc* descs, void* hip_stream, bt_si
     h->use_graph = !h->inst.empty();
     for (auto& I : h->inst) h->use_graph = h->use_graph && (I.desc.flags & BT_GRAPH);
     if (e != hipSuccess) {
-        hipFree(h->ws); hipFree(h->inv_pool); hipFree(h->status);
+        if (h->own_block) hipFree(h->block);
         return hip_err(nullptr, e, "create");
     }
     *out = h.release();
@@ -1771,9 +1848,9 @@ size_t bt_si_sq_workspace_bytes(const bt_desc* desc) {
 
 size_t bt_si_sq_batch_workspace_bytes(int32_t count, const bt_desc* descs) {
     std::vector<Instance> inst;
-    size_t ws = 0, inv = 0;
-    if (plan_instances(count, descs, inst, ws, inv, nullptr) != BT_OK) return 0;
-    return ws + inv + 4096;
+    size_t ws = 0, inv = 0, prog = 0;
+    if (plan_instances(count, descs, inst, ws, inv, nullptr, &prog) != BT_OK) return 0;
+    return block_layout(ws, inv, prog).total;
 }
 
 bt_status bt_si_sq_partition_bounds(const bt_desc* desc, int32_t* bounds_out) {
@@ -1809,6 +1886,15 @@ bt_status bt_si_sq_create(const bt_desc* desc, void* hip_stream, bt_si_sq_handle
 bt_status bt_si_sq_batch_create(int32_t count, const bt_desc* descs, void* hip_stream,
                                 bt_si_sq_handle* out) {
     return create_handle(count, descs, hip_stream, out);
+}
+
+bt_status bt_si_sq_batch_create_in(int32_t count, const bt_desc* descs, void* hip_stream, void* workspace,
+                                   size_t workspace_bytes, bt_si_sq_handle* out) {
+    if (!workspace) {
+        if (out) *out = nullptr;
+        return set_err(nullptr, BT_ERR_INVALID, "workspace is null");
+    }
+    return create_handle(count, descs, hip_stream, out, workspace, workspace_bytes);
 }
 
 bt_status bt_si_sq_factor(bt_si_sq_handle h, const bt_blocks* A, bt_blocks* XR) {
@@ -1911,11 +1997,13 @@ bt_status bt_si_sq_sync(bt_si_sq_handle h) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "hipStreamSynchronize");
     DevStatus s{0, 0};
-    e = hipMemcpy(&s, h->status, sizeof s, hipMemcpyDeviceToHost);
+    e = hipMemcpyAsync(&s, h->status, sizeof s, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(h, e, "status readback");
     if (s.code != 0) {
         DevStatus z{0, 0};
-        hipMemcpy(h->status, &z, sizeof z, hipMemcpyHostToDevice);
+        if (hipMemcpyAsync(h->status, &z, sizeof z, hipMemcpyHostToDevice, h->stream) == hipSuccess)
+            hipStreamSynchronize(h->stream);
         const int inst = s.tag >> 16, blk = s.tag & 0xffff;
         const bool tip = inst < (int)h->inst.size() && blk == h->inst[inst].D.n;
         char buf[200];
@@ -1937,7 +2025,6 @@ bt_status bt_si_sq_destroy(bt_si_sq_handle h) {
     hipStreamSynchronize(h->astream);
     if (h->gstream) hipStreamSynchronize(h->gstream);
     for (auto& c : h->cache) free_cached(h, c);
-    if (h->host_stage) hipHostFree(h->host_stage);
     if (h->upload_done) hipEventDestroy(h->upload_done);
     if (h->ev_start) hipEventDestroy(h->ev_start);
     if (h->ev_end) hipEventDestroy(h->ev_end);
@@ -1946,9 +2033,7 @@ bt_status bt_si_sq_destroy(bt_si_sq_handle h) {
     if (h->astream) hipStreamDestroy(h->astream);
     if (h->gstream) hipStreamDestroy(h->gstream);
     for (auto ev : h->ev_pool) hipEventDestroy(ev);
-    hipFree(h->ws);
-    hipFree(h->inv_pool);
-    hipFree(h->status);
+    if (h->own_block) hipFree(h->block);
     delete h;
     return BT_OK;
 }

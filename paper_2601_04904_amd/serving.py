@@ -4,7 +4,12 @@ NEGF sweep arriving over time).
 Requests of different (n, b, a, precision) arrive on a clock.  The engine
 keeps a device-memory budget: a request is admitted when its footprint (the
 library's workspace for it plus its input and output blocks) fits beside the
-requests already admitted.  Admitted requests are grouped into waves; each
+requests already admitted.  The memory itself is one device allocation made
+when the replay starts (an arena the size of the budget): each wave takes one
+range of it for its requests' blocks and its batch handle's workspace
+(bt_si_sq_batch_create_in) and returns it when done, so no device memory is
+allocated or released while waves run (either would wait for the whole
+device).  Admitted requests are grouped into waves; each
 wave is one batch handle (all its instances in one schedule) run by a worker
 thread on its own HIP stream, so up to `max_inflight` waves overlap on the
 device and requests that arrive while a wave runs are admitted as soon as a
@@ -22,7 +27,7 @@ from collections import deque
 from dataclasses import dataclass, field
 
 from . import solver as S
-from .synth_device import gen_problem_device, gen_rhs_device
+from .synth_device import CHUNK, gen_problem_device, gen_rhs_device
 
 
 @dataclass
@@ -67,11 +72,78 @@ class Request:
         return ex * (1.0 + 0.6 * (self.nrhs - 1))
 
 
+ALIGN = 256
+
+
+def _al(x: int) -> int:
+    return (x + ALIGN - 1) // ALIGN * ALIGN
+
+
+def field_bytes(n: int, b: int, a: int):
+    """Bytes of the six fields of one matrix's blocks (complex128)."""
+    m = max(n - 1, 0)
+    return [16 * n * b * b, 16 * m * b * b, 16 * m * b * b, 16 * n * b * a, 16 * n * a * b, 16 * a * a]
+
+
+def blocks_bytes(n: int, b: int, a: int) -> int:
+    return sum(_al(x) for x in field_bytes(n, b, a))
+
+
+def request_io_bytes(req: Request) -> int:
+    """A, B, XR, XL (+ B2, XL2 for a second right-hand side)."""
+    return (4 + 2 * (req.nrhs - 1)) * blocks_bytes(req.n, req.b, req.a)
+
+
 def request_footprint(req: Request) -> int:
     ws = S.batch_workspace_bytes([req.spec()])
-    io = 16 * req.pattern_elems() * (4 + 2 * (req.nrhs - 1))   # A, B, XR, XL (+ B2, XL2)
-    gen = 16 * 3 * req.n * req.b * req.b                         # transient blocks of the input generator
-    return ws + io + gen
+    gen = 16 * 4 * min(req.n, CHUNK) * req.b * req.b             # transient blocks of the input generator
+    return ws + request_io_bytes(req) + gen
+
+
+class DeviceArena:
+    """One device allocation handed out in ranges: first fit, and a released
+    range is merged with free neighbours.  Offsets and sizes are multiples
+    of 256 bytes.  Not thread-safe (the engine calls it under its lock)."""
+
+    def __init__(self, torch, nbytes: int):
+        self.buf = torch.empty(_al(nbytes), dtype=torch.uint8, device="cuda")
+        self.size = self.buf.numel()
+        self.free = [(0, self.size)]          # sorted (offset, size)
+
+    def alloc(self, nbytes: int):
+        n = _al(nbytes)
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + n, sz - n)
+                return o
+        return None
+
+    def release(self, off: int, nbytes: int):
+        n = _al(nbytes)
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, sz in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + sz)
+            else:
+                merged.append((o, sz))
+        self.free = merged
+
+
+def carve_blocks(buf, off: int, n: int, b: int, a: int):
+    """DeviceBlocks viewing buf[off:], fields one after another (256-aligned);
+    returns the blocks and the offset after them."""
+    import torch
+    shapes = [(n, b, b), (max(n - 1, 0), b, b), (max(n - 1, 0), b, b), (n, b, a), (n, a, b), (a, a)]
+    views = []
+    for shp, nb in zip(shapes, field_bytes(n, b, a)):
+        views.append(buf[off:off + nb].view(torch.complex128).view(shp))
+        off += _al(nb)
+    return S.DeviceBlocks(*views), off
 
 
 class PrecisionRouter:
@@ -142,7 +214,7 @@ class PrecisionRouter:
 
 class ServingEngine:
     def __init__(self, budget_bytes: int, max_inflight: int = 2, max_wave: int = 16,
-                 input_fn=None, router: PrecisionRouter | None = None, log=None):
+                 input_fn=None, router: PrecisionRouter | None = None, log=None, use_arena: bool = True):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -161,18 +233,23 @@ class ServingEngine:
         self.max_used = 0
         self.router = router
         self.oom_retries = 0
-        self.release_above = 8 << 30      # cached-but-unused torch memory released before a wave
-        self.size_ratio = 8.0             # largest work ratio between requests of one wave
+        self.size_ratio = 4.0             # largest work ratio between requests of one wave
+        self.chain_ratio = 1.5            # largest ratio of block counts in one wave
         self.threads = []
         self.log = log                    # callable taking a progress line (one per finished wave)
+        self.use_arena = use_arena
+        self.arena = None                 # DeviceArena of the budget, made when the replay starts
+        self.arena_misses = 0             # waves whose range did not fit the arena (own allocation)
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
     @staticmethod
-    def _device_inputs(req: Request):
-        A, B = gen_problem_device(req.n, req.b, req.a, req.E, req.eta, req.seed)
-        B2 = gen_rhs_device(req.n, req.b, req.a, req.seed + 1) if req.nrhs > 1 else None
+    def _device_inputs(req: Request, out=None):
+        """(A, B, B2) of a request, into out = (A, B, B2) if given."""
+        oA, oB, oB2 = out if out is not None else (None, None, None)
+        A, B = gen_problem_device(req.n, req.b, req.a, req.E, req.eta, req.seed, out=(oA, oB))
+        B2 = gen_rhs_device(req.n, req.b, req.a, req.seed + 1, out=oB2) if req.nrhs > 1 else None
         return A, B, B2
 
     def submit(self, req: Request):
@@ -183,50 +260,104 @@ class ServingEngine:
         with self.lock:
             self.pending.append(req)
 
+    def _compatible(self, head, r) -> bool:
+        """Requests that share a wave well: similar work (within size_ratio)
+        and similar chains of block inverses (block counts within
+        chain_ratio), so that the instances' inverses and products share the
+        schedule's launches level by level and none waits long for the
+        slowest."""
+        ratio = r.flops() / max(head.flops(), 1.0)
+        if ratio > self.size_ratio or ratio < 1.0 / self.size_ratio:
+            return False
+        chain = r.n / max(head.n, 1)
+        return 1.0 / self.chain_ratio <= chain <= self.chain_ratio
+
     def _take_wave(self):
-        """FIFO requests that fit the memory budget (head-of-line order kept).
-        A wave finishes with its slowest request, so it stops at the first
-        request whose work differs from the wave's first one by more than
-        `size_ratio` either way; that request heads the next wave."""
+        """The oldest pending request heads the wave (so no request is passed
+        over for good); every later pending request compatible with it joins,
+        in arrival order, while the wave has room and the memory budget
+        allows.  The others keep their places for the next waves."""
         wave = []
-        while self.pending and len(wave) < self.max_wave:
-            r = self.pending[0]
-            if self.used + r.footprint > self.budget:
-                break
-            if wave:
-                ratio = r.flops() / max(wave[0].flops(), 1.0)
-                if ratio > self.size_ratio or ratio < 1.0 / self.size_ratio:
-                    break
-            self.pending.popleft()
-            self.used += r.footprint
-            self.max_used = max(self.max_used, self.used)
-            r.t_admit = self.now()
-            wave.append(r)
+        if not self.pending:
+            return wave
+        head = self.pending[0]
+        if self.used + head.footprint > self.budget:
+            return wave
+        keep = deque()
+        while self.pending:
+            r = self.pending.popleft()
+            fits = len(wave) < self.max_wave and self.used + r.footprint <= self.budget
+            if fits and (not wave or self._compatible(head, r)):
+                self.used += r.footprint
+                self.max_used = max(self.max_used, self.used)
+                r.t_admit = self.now()
+                wave.append(r)
+            else:
+                keep.append(r)
+        self.pending = keep
         return wave
+
+    def _wave_memory(self, wave, specs):
+        """One range for the wave: every request's blocks, then the batch
+        handle's workspace.  From the arena when it fits, else (fragmented
+        arena) an allocation of its own.  Returns (buffer, release)."""
+        torch = self.torch
+        total = sum(request_io_bytes(r) for r in wave) + _al(S.batch_workspace_bytes(specs))
+        if self.arena is not None:
+            with self.lock:
+                off = self.arena.alloc(total)
+            if off is not None:
+                def release(off=off):
+                    with self.lock:
+                        self.arena.release(off, total)
+                return self.arena.buf[off:off + _al(total)], release
+            self.arena_misses += 1
+        buf = torch.empty(_al(total), dtype=torch.uint8, device="cuda")
+        return buf, (lambda: None)
 
     def _run_wave(self, wave):
         torch = self.torch
         stream = torch.cuda.Stream()
         bs = None
+        phases = None
+        release = None
         try:
             with torch.cuda.stream(stream):
                 t_start = self.now()
                 for r in wave:
                     r.t_start = t_start
-                inputs = [self.input_fn(r) for r in wave]
-                XR = [S.DeviceBlocks.empty(r.n, r.b, r.a) for r in wave]
-                XL = [S.DeviceBlocks.empty(r.n, r.b, r.a) for r in wave]
                 if self.router is not None:
                     for r in wave:
                         if r.precision == "mixed":
                             r.run_precision = self.router.choose(r.eta, r.a, r.flops())
-                bs = self._batch_solver([r.spec() for r in wave], stream)
+                specs = [r.spec() for r in wave]
+                buf, release = self._wave_memory(wave, specs)
+                off = 0
+                inputs, XR, XL, XL2s = [], [], [], []
+                for r in wave:
+                    A, off = carve_blocks(buf, off, r.n, r.b, r.a)
+                    B, off = carve_blocks(buf, off, r.n, r.b, r.a)
+                    xr, off = carve_blocks(buf, off, r.n, r.b, r.a)
+                    xl, off = carve_blocks(buf, off, r.n, r.b, r.a)
+                    B2 = xl2 = None
+                    if r.nrhs > 1:
+                        B2, off = carve_blocks(buf, off, r.n, r.b, r.a)
+                        xl2, off = carve_blocks(buf, off, r.n, r.b, r.a)
+                    inputs.append(self.input_fn(r, (A, B, B2)))
+                    XR.append(xr)
+                    XL.append(xl)
+                    XL2s.append(xl2)
+                ws = buf[off:]
+                stream.synchronize()
+                t_inputs = self.now()
+                bs = S.BatchSolver(specs, stream=stream, workspace=ws)
+                t_created = self.now()
                 err, fb = bs.solve([x[0] for x in inputs], [x[1] for x in inputs], XR, XL)
                 errs = [[e] for e in err]
                 fbs = [[f] for f in fb]
                 XL2 = None
                 if any(r.nrhs > 1 for r in wave):
-                    XL2 = [S.DeviceBlocks.empty(r.n, r.b, r.a) if r.nrhs > 1 else None for r in wave]
+                    XL2 = XL2s
                     e2, f2 = bs.selected_solve([x[2] for x in inputs], XL2)
                     for i, r in enumerate(wave):
                         if r.nrhs > 1:
@@ -236,6 +367,7 @@ class ServingEngine:
                 t_done = self.now()
                 bs.destroy()
                 bs = None
+                phases = (t_inputs - t_start, t_created - t_inputs, t_done - t_created, self.now() - t_done)
                 if self.router is not None:
                     for i, r in enumerate(wave):
                         if r.spec()["precision"] == S.BT_MIXED:
@@ -244,8 +376,9 @@ class ServingEngine:
                     r.t_done = t_done
                     r.err = errs[i]
                     r.fallback = fbs[i]
-                    if r.keep_outputs:
-                        r.outputs = (XR[i], XL[i], XL2[i] if XL2 else None)
+                    if r.keep_outputs:        # copies: the wave's range is reused afterwards
+                        r.outputs = tuple(_copy_blocks(x) for x in (XR[i], XL[i], XL2[i] if XL2 else None))
+                stream.synchronize()
                 del inputs
         except Exception as ex:  # keep the loop alive; report at the end
             self.errors.append(repr(ex))
@@ -257,6 +390,9 @@ class ServingEngine:
                     bs.destroy()
                 except Exception as ex:
                     self.errors.append(repr(ex))
+            if release is not None:
+                stream.synchronize()      # nothing of the wave may still use its range
+                release()
             with self.cv:
                 for r in wave:
                     self.used -= r.footprint
@@ -265,25 +401,12 @@ class ServingEngine:
                 ndone = len(self.done)
                 self.cv.notify_all()
             if self.log is not None:
+                ph = phases
+                detail = (f": inputs {ph[0]:.3f} s, create {ph[1]:.3f} s, solves {ph[2]:.3f} s, "
+                          f"destroy {ph[3]:.3f} s, {sum(r.flops() for r in wave) / 1e12:.1f} TFLOP"
+                          if ph else "")
                 self.log(f"[serve] wave of {len(wave)} finished at {self.now():.2f} s "
-                         f"({ndone} requests done)")
-
-    def _batch_solver(self, specs, stream):
-        """The library allocates its workspace outside torch's caching allocator,
-        so blocks that torch has cached (the input generator's temporaries) are
-        released first; an allocation failure is retried once after that."""
-        torch = self.torch
-        if torch.cuda.memory_reserved() - torch.cuda.memory_allocated() > self.release_above:
-            torch.cuda.empty_cache()
-        try:
-            return S.BatchSolver(specs, stream=stream)
-        except S.BTError as ex:
-            if "OOM" not in str(ex):
-                raise
-            self.oom_retries += 1
-            torch.cuda.synchronize()
-            torch.cuda.empty_cache()
-            return S.BatchSolver(specs, stream=stream)
+                         f"({ndone} requests done){detail}")
 
     def dispatch(self) -> bool:
         """Start a wave if a worker is free and requests fit; returns True if one started."""
@@ -305,6 +428,8 @@ class ServingEngine:
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             r.footprint = request_footprint(r)
+        if self.use_arena and self.arena is None:
+            self.arena = DeviceArena(self.torch, self.budget)
         self.t0 = time.perf_counter()
         i = 0
         total = len(reqs)
@@ -323,7 +448,14 @@ class ServingEngine:
         for th in self.threads:          # no worker outlives the replay
             th.join()
         self.threads = []
+        self.arena = None                # back to torch's cache for the next engine
         return summarize(self.done, wall)
+
+
+def _copy_blocks(X):
+    if X is None:
+        return None
+    return S.DeviceBlocks(*(getattr(X, f).clone() for f in S.FIELDS))
 
 
 def summarize(done, wall):

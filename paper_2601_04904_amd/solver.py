@@ -249,10 +249,13 @@ class BatchSolver:
     """bt_si_sq_batch_create / _batch_solve: many uneven instances in one schedule.
 
     specs: list of dicts with n, b, a and optionally partitions, bounds,
-    precision, tol.
+    precision, tol, flags, sizes.  workspace: None (the library allocates
+    the handle's device memory), or a contiguous device tensor of at least
+    batch_workspace_bytes(specs) bytes that the handle uses instead
+    (bt_si_sq_batch_create_in; kept alive by the solver until destroy).
     """
 
-    def __init__(self, specs, stream=None):
+    def __init__(self, specs, stream=None, workspace=None):
         torch = _torch()
         self.count = len(specs)
         self._descs = [make_desc(sp["n"], sp.get("b", 0), sp.get("a", 0), sp.get("partitions", 1),
@@ -263,8 +266,15 @@ class BatchSolver:
         self._arr = arr
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
-        check(_lib.lib().bt_si_sq_batch_create(self.count, arr, C.c_void_p(self.stream.cuda_stream),
-                                               C.byref(h)))
+        self._workspace = workspace
+        if workspace is None:
+            check(_lib.lib().bt_si_sq_batch_create(self.count, arr, C.c_void_p(self.stream.cuda_stream),
+                                                   C.byref(h)))
+        else:
+            assert workspace.is_cuda and workspace.is_contiguous()
+            nbytes = workspace.numel() * workspace.element_size()
+            check(_lib.lib().bt_si_sq_batch_create_in(self.count, arr, C.c_void_p(self.stream.cuda_stream),
+                                                      C.c_void_p(workspace.data_ptr()), nbytes, C.byref(h)))
         self._h = h
 
     def solve(self, A, B, XR, XL):
@@ -306,6 +316,7 @@ class BatchSolver:
         if getattr(self, "_h", None):
             _lib.lib().bt_si_sq_destroy(self._h)
             self._h = None
+        self._workspace = None      # the caller's memory may be reused only now
 
     def __del__(self):
         try:

@@ -326,3 +326,23 @@ def test_block_sizes_descriptor():
         d = LB.make_desc(3, 0, 0, 1, None, sizes=bad)
         assert L.bt_si_sq_workspace_bytes(C.byref(d)) == 0
         assert b"block_sizes" in L.bt_si_sq_last_error(None)
+
+
+def test_batch_create_in_rejects_bad_workspace_before_any_device_call():
+    """bt_si_sq_batch_create_in checks the caller's workspace on the host:
+    null, too small or not 256-byte aligned is BT_ERR_INVALID (the fake
+    addresses are never dereferenced)."""
+    from paper_2601_04904_amd import _lib as LB
+    L = _lib.lib()
+    d = make_desc(12, 32, 8, 2)
+    need = L.bt_si_sq_batch_workspace_bytes(1, C.byref(d))
+    assert need > 0 and need == L.bt_si_sq_workspace_bytes(C.byref(d))
+    h = C.c_void_p()
+    assert L.bt_si_sq_batch_create_in(1, C.byref(d), None, None, need, C.byref(h)) == BT_ERR_INVALID
+    assert L.bt_si_sq_batch_create_in(1, C.byref(d), None, C.c_void_p(1 << 40), need - 1,
+                                      C.byref(h)) == BT_ERR_INVALID
+    assert b"smaller" in L.bt_si_sq_last_error(None)
+    assert L.bt_si_sq_batch_create_in(1, C.byref(d), None, C.c_void_p((1 << 40) + 64), need,
+                                      C.byref(h)) == BT_ERR_INVALID
+    assert b"aligned" in L.bt_si_sq_last_error(None)
+    assert not h.value

@@ -77,3 +77,33 @@ def test_batch_mixed_and_fp64_instances(S):
             assert e <= 1e-4
         else:
             assert e < 1e-11
+
+
+def test_batch_with_caller_workspace_matches_library_allocation(S):
+    """bt_si_sq_batch_create_in: the handle works in a torch-allocated
+    workspace and gives the same bits as a handle that allocates its own;
+    the workspace block is reused by a second handle after destroy."""
+    import torch
+    specs = [dict(n=10, b=40, a=12, partitions=2), dict(n=7, b=24, a=0, partitions=1),
+             dict(n=12, b=33, a=0, partitions=3)]
+    probs = [gen_problem(sp["n"], sp["b"], sp["a"], E=0.2, eta=1e-3, seed=200 + i) for i, sp in enumerate(specs)]
+    dA = [S.DeviceBlocks.from_host(A) for A, _ in probs]
+    dB = [S.DeviceBlocks.from_host(B) for _, B in probs]
+    outs = []
+    ws = torch.empty(S.batch_workspace_bytes(specs), dtype=torch.uint8, device="cuda")
+    for workspace in (None, ws, ws):
+        XR = [S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]) for sp in specs]
+        XL = [S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]) for sp in specs]
+        bs = S.BatchSolver(specs, workspace=workspace)
+        bs.solve(dA, dB, XR, XL)
+        bs.sync()
+        bs.destroy()
+        outs.append([(x.to_host(), y.to_host()) for x, y in zip(XR, XL)])
+    for run in outs[1:]:
+        for (xr0, xl0), (xr, xl) in zip(outs[0], run):
+            for f in S.FIELDS:
+                assert np.array_equal(getattr(xr, f), getattr(xr0, f))
+                assert np.array_equal(getattr(xl, f), getattr(xl0, f))
+    for (A, B), (xr, xl) in zip(probs, outs[0]):
+        R0, L0 = oracle.solve_dense(A, B)
+        assert rel_err(xr, R0) < 1e-11 and rel_err(xl, L0) < 1e-11

@@ -36,7 +36,29 @@ def test_request_footprint_counts_workspace_io_and_generator():
     req = serving.Request(rid=0, n=8, b=64, a=0, nrhs=2)
     ws = S.batch_workspace_bytes([req.spec()])
     fp = serving.request_footprint(req)
-    assert fp == ws + 16 * req.pattern_elems() * 6 + 16 * 3 * 8 * 64 * 64
+    # six matrices of blocks (A, B, XR, XL, B2, XL2), each field 256-aligned;
+    # the generator's temporaries for CHUNK blocks at a time
+    assert serving.blocks_bytes(8, 64, 0) == 16 * req.pattern_elems()
+    assert fp == ws + 16 * req.pattern_elems() * 6 + 16 * 4 * 8 * 64 * 64
+
+
+def test_device_arena_first_fit_and_merge():
+    arena = serving.DeviceArena.__new__(serving.DeviceArena)
+    arena.size = 4096
+    arena.free = [(0, 4096)]
+    a = arena.alloc(1000)          # rounded to 1024
+    b = arena.alloc(256)
+    c = arena.alloc(2048)
+    assert (a, b, c) == (0, 1024, 1280)
+    assert arena.alloc(1024) is None          # only 768 left
+    arena.release(b, 256)
+    assert arena.alloc(800) is None            # a 256 hole and 768 at the end
+    arena.release(a, 1000)                     # merges with the hole: [0, 1280)
+    assert arena.free[0] == (0, 1280)
+    assert arena.alloc(1280) == 0
+    arena.release(0, 1280)
+    arena.release(c, 2048)
+    assert arena.free == [(0, 4096)]
 
 
 def test_requests_from_trace_keep_order_and_fields():
@@ -57,18 +79,40 @@ def test_router_probes_only_cheap_requests():
     assert r.choose(1e-3, 0, flops=5e9) == S.BT_MIXED    # now known to pass
 
 
-def test_wave_stops_at_very_different_request():
+def _bare_engine():
     eng = serving.ServingEngine.__new__(serving.ServingEngine)
     eng.pending = serving.deque()
     eng.used, eng.budget, eng.max_wave, eng.max_used = 0, 1 << 60, 8, 0
-    eng.size_ratio = 8.0
+    eng.size_ratio, eng.chain_ratio = 4.0, 1.5
     eng.t0 = 0.0
     eng.now = lambda: 0.0
+    return eng
+
+
+def test_wave_groups_compatible_requests_and_keeps_the_rest_in_order():
+    eng = _bare_engine()
     small = [serving.Request(rid=i, n=8, b=64, a=0) for i in range(3)]
     big = serving.Request(rid=9, n=64, b=512, a=0)
-    for r in small[:2] + [big] + small[2:]:
+    long_chain = serving.Request(rid=7, n=16, b=48, a=0)    # similar work, twice the chain
+    for r in small[:2] + [big, long_chain] + small[2:]:
         r.footprint = 1
         eng.pending.append(r)
     wave = eng._take_wave()
-    assert [r.rid for r in wave] == [0, 1]
-    assert eng.pending[0].rid == 9
+    assert [r.rid for r in wave] == [0, 1, 2]
+    assert [r.rid for r in eng.pending] == [9, 7]
+    # the oldest remaining request heads the next wave
+    assert [r.rid for r in eng._take_wave()] == [9]
+    assert [r.rid for r in eng._take_wave()] == [7]
+
+
+def test_wave_respects_memory_budget_and_size():
+    eng = _bare_engine()
+    eng.budget, eng.max_wave = 10, 2
+    reqs = [serving.Request(rid=i, n=8, b=64, a=0) for i in range(4)]
+    for r, fp in zip(reqs, (4, 7, 3, 2)):
+        r.footprint = fp
+        eng.pending.append(r)
+    wave = eng._take_wave()
+    assert [r.rid for r in wave] == [0, 2] and eng.used == 7
+    assert [r.rid for r in eng.pending] == [1, 3]
+    assert eng._take_wave() == []          # the head (7 units) does not fit beside 7 in use
