@@ -269,7 +269,7 @@ def bench_serve(args, torch, S):
         stats["waves"] = eng.waves
         stats["errors"] = eng.errors
         stats["routed_to_fp64"] = eng.router.routed
-        stats["arena_misses"] = eng.arena_misses
+        stats["arena_waits"] = eng.arena_waits
         log(f"[bench] serving at {rate:g}/s: {stats}")
         # plain RGF on the same trace: FP64, sequential sweep, one request at a
         # time, one launch per single-term product, one stream

@@ -95,7 +95,12 @@ def request_io_bytes(req: Request) -> int:
 
 
 def request_footprint(req: Request) -> int:
-    ws = S.batch_workspace_bytes([req.spec()])
+    """Device bytes a request may hold: the workspace of either precision it
+    may be routed to, its blocks, and the generator's transient blocks."""
+    spec = req.spec()
+    ws = S.batch_workspace_bytes([spec])
+    if req.precision == "mixed":
+        ws = max(ws, S.batch_workspace_bytes([dict(spec, precision=S.BT_FP64)]))
     gen = 16 * 4 * min(req.n, CHUNK) * req.b * req.b             # transient blocks of the input generator
     return ws + request_io_bytes(req) + gen
 
@@ -239,7 +244,7 @@ class ServingEngine:
         self.log = log                    # callable taking a progress line (one per finished wave)
         self.use_arena = use_arena
         self.arena = None                 # DeviceArena of the budget, made when the replay starts
-        self.arena_misses = 0             # waves whose range did not fit the arena (own allocation)
+        self.arena_waits = 0              # times the queue head waited for an arena range
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -297,25 +302,49 @@ class ServingEngine:
         self.pending = keep
         return wave
 
-    def _wave_memory(self, wave, specs):
-        """One range for the wave: every request's blocks, then the batch
-        handle's workspace.  From the arena when it fits, else (fragmented
-        arena) an allocation of its own.  Returns (buffer, release)."""
-        torch = self.torch
-        total = sum(request_io_bytes(r) for r in wave) + _al(S.batch_workspace_bytes(specs))
-        if self.arena is not None:
-            with self.lock:
-                off = self.arena.alloc(total)
+    def _wave_bytes(self, wave) -> int:
+        """Bytes of the wave's one range: every request's blocks, then the
+        batch handle's workspace."""
+        specs = [r.spec() for r in wave]
+        return sum(request_io_bytes(r) for r in wave) + _al(S.batch_workspace_bytes(specs))
+
+    def _reserve(self, wave):
+        """Called under the lock.  Takes the wave's range from the arena; when
+        the arena (fragmented by the waves in flight) has no such range, the
+        latest joiners go back to the queue one by one until the rest fits.
+        Returns (wave, (offset, bytes)), or ([], None) with every request
+        back in the queue when not even the head fits: the wave then waits
+        for a range to be released instead of allocating outside the arena."""
+        back = []
+        while wave:
+            total = self._wave_bytes(wave)
+            off = self.arena.alloc(total)
             if off is not None:
-                def release(off=off):
-                    with self.lock:
-                        self.arena.release(off, total)
-                return self.arena.buf[off:off + _al(total)], release
-            self.arena_misses += 1
-        buf = torch.empty(_al(total), dtype=torch.uint8, device="cuda")
+                break
+            back.append(wave.pop())
+        if back:
+            for r in back:
+                self.used -= r.footprint
+            self.pending = deque(sorted(list(self.pending) + back, key=lambda r: (r.arrival, r.rid)))
+        if not wave:
+            self.arena_waits += 1
+            return [], None
+        return wave, (off, total)
+
+    def _wave_memory(self, wave, reservation):
+        """(buffer, release) of the wave: its arena range, or with no arena an
+        allocation of its own."""
+        if reservation is not None:
+            off, total = reservation
+
+            def release():
+                with self.lock:
+                    self.arena.release(off, total)
+            return self.arena.buf[off:off + _al(total)], release
+        buf = self.torch.empty(_al(self._wave_bytes(wave)), dtype=self.torch.uint8, device="cuda")
         return buf, (lambda: None)
 
-    def _run_wave(self, wave):
+    def _run_wave(self, wave, reservation=None):
         torch = self.torch
         stream = torch.cuda.Stream()
         bs = None
@@ -326,12 +355,8 @@ class ServingEngine:
                 t_start = self.now()
                 for r in wave:
                     r.t_start = t_start
-                if self.router is not None:
-                    for r in wave:
-                        if r.precision == "mixed":
-                            r.run_precision = self.router.choose(r.eta, r.a, r.flops())
                 specs = [r.spec() for r in wave]
-                buf, release = self._wave_memory(wave, specs)
+                buf, release = self._wave_memory(wave, reservation)
                 off = 0
                 inputs, XR, XL, XL2s = [], [], [], []
                 for r in wave:
@@ -369,9 +394,10 @@ class ServingEngine:
                 bs = None
                 phases = (t_inputs - t_start, t_created - t_inputs, t_done - t_created, self.now() - t_done)
                 if self.router is not None:
-                    for i, r in enumerate(wave):
-                        if r.spec()["precision"] == S.BT_MIXED:
-                            self.router.record(r.eta, r.a, bool(fbs[i][0]))
+                    with self.lock:
+                        for i, r in enumerate(wave):
+                            if r.spec()["precision"] == S.BT_MIXED:
+                                self.router.record(r.eta, r.a, bool(fbs[i][0]))
                 for i, r in enumerate(wave):
                     r.t_done = t_done
                     r.err = errs[i]
@@ -416,9 +442,18 @@ class ServingEngine:
             wave = self._take_wave()
             if not wave:
                 return False
+            if self.router is not None:     # the precision fixes the workspace size
+                for r in wave:
+                    if r.precision == "mixed":
+                        r.run_precision = self.router.choose(r.eta, r.a, r.flops())
+            reservation = None
+            if self.arena is not None:
+                wave, reservation = self._reserve(wave)
+                if not wave:
+                    return False
             self.busy += 1
             self.waves += 1
-        th = threading.Thread(target=self._run_wave, args=(wave,))
+        th = threading.Thread(target=self._run_wave, args=(wave, reservation))
         self.threads.append(th)
         th.start()
         return True

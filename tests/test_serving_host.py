@@ -116,3 +116,46 @@ def test_wave_respects_memory_budget_and_size():
     assert [r.rid for r in wave] == [0, 2] and eng.used == 7
     assert [r.rid for r in eng.pending] == [1, 3]
     assert eng._take_wave() == []          # the head (7 units) does not fit beside 7 in use
+
+
+def _arena(size):
+    arena = serving.DeviceArena.__new__(serving.DeviceArena)
+    arena.size = size
+    arena.free = [(0, size)]
+    return arena
+
+
+def test_reserve_sends_joiners_back_when_the_arena_is_fragmented():
+    eng = _bare_engine()
+    eng.arena_waits = 0
+    reqs = [serving.Request(rid=i, n=8, b=64, a=0, arrival=0.1 * i) for i in range(4)]
+    one = eng._wave_bytes(reqs[:1])
+    two = eng._wave_bytes(reqs[:2])
+    assert two > one
+    for r in reqs:
+        r.footprint = 1
+        eng.pending.append(r)
+    wave = eng._take_wave()
+    assert [r.rid for r in wave] == [0, 1, 2, 3] and eng.used == 4
+    # room for the first two requests' range only
+    eng.arena = _arena(serving._al(two))
+    wave, (off, total) = eng._reserve(wave)
+    assert [r.rid for r in wave] == [0, 1] and (off, total) == (0, two)
+    assert [r.rid for r in eng.pending] == [2, 3] and eng.used == 2
+    # nothing left: the head waits in the queue, in arrival order
+    eng.pending.append(serving.Request(rid=5, n=8, b=64, a=0, arrival=0.45))
+    eng.pending[-1].footprint = 1
+    head = eng._take_wave()
+    assert [r.rid for r in head] == [2, 3, 5]
+    assert eng._reserve(head) == ([], None)
+    assert [r.rid for r in eng.pending] == [2, 3, 5] and eng.used == 2 and eng.arena_waits == 1
+    eng.arena.release(off, total)
+    wave, res = eng._reserve(eng._take_wave())
+    assert [r.rid for r in wave] == [2, 3] and res == (0, two)
+
+
+def test_mixed_request_footprint_covers_either_precision():
+    req = serving.Request(rid=0, n=8, b=64, a=32, precision="mixed")
+    fp64 = serving.Request(rid=1, n=8, b=64, a=32)
+    ws = max(S.batch_workspace_bytes([req.spec()]), S.batch_workspace_bytes([fp64.spec()]))
+    assert serving.request_footprint(req) - serving.request_io_bytes(req) - 16 * 4 * 8 * 64 * 64 == ws
