@@ -343,6 +343,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--inflight", type=int, default=2)
     ap.add_argument("--max-wave", type=int, default=8)
+    ap.add_argument("--fused", type=int, default=1,
+                    help="1: workloads with blocks and tip <= 64 also run the sequential sweep as one "
+                         "fused launch (BT_FUSED), a candidate for the value")
     ap.add_argument("--antihermitian", type=int, default=1,
                     help="1: also time the reported form with BT_SIGMA_ANTIHERMITIAN (the synthetic "
                          "Sigma^< is anti-Hermitian) and report it beside the value")
@@ -416,22 +419,30 @@ def main():
     dA, dB = Blocks.from_host(A), Blocks.from_host(B)
     XR, XL = new_blocks(), new_blocks()
 
+    # forms: (key, partitions, extra flags); with blocks and tip of at most
+    # 64 the sequential sweep also runs as one fused launch (BT_FUSED)
+    fusable = max(sizes or [b]) <= 64 and a <= 64
+    variants = [(f"P{q}", q, 0) for q in forms + extra]
+    if fusable and args.fused:
+        variants.append(("P1_fused", 1, S.BT_FUSED))
+    named = [k for k, q, _ in variants if q in forms]
     timed = {}
-    for P in forms + extra:
-        sol = S.Solver(n, b, a, partitions=P, flags=args.flags, sizes=sizes)
+    for key, q, fl in variants:
+        sol = S.Solver(n, b, a, partitions=q, flags=args.flags | fl, sizes=sizes)
         el, lt = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
-        exP, usP = S.flops(n, b, a, P, sizes=sizes)
-        timed[P] = dict(elapsed=el, lat=lt, launches=sol.last_launch_count(), ex=exP, us=usP)
+        exP, usP = S.flops(n, b, a, q, sizes=sizes)
+        timed[key] = dict(P=q, flags=fl, elapsed=el, lat=lt, launches=sol.last_launch_count(), ex=exP, us=usP)
         sol.destroy()
-        log(f"[bench] P={P}: {1e3 * el / args.steps:.2f} ms/solve, {timed[P]['launches']} launches/solve")
-    P = min(forms, key=lambda q: timed[q]["elapsed"])
-    elapsed, lat, launches = timed[P]["elapsed"], timed[P]["lat"], timed[P]["launches"]
-    ex, us = timed[P]["ex"], timed[P]["us"]
+        log(f"[bench] {key}: {1e3 * el / args.steps:.2f} ms/solve, {timed[key]['launches']} launches/solve")
+    best = min(named, key=lambda k: timed[k]["elapsed"])
+    P, pflags = timed[best]["P"], timed[best]["flags"]
+    elapsed, lat, launches = timed[best]["elapsed"], timed[best]["lat"], timed[best]["launches"]
+    ex, us = timed[best]["ex"], timed[best]["us"]
     ms = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel of the reported form, from HIP events
     # recorded around each launch on the stream it runs on
-    sol = S.Solver(n, b, a, partitions=P, sizes=sizes)
+    sol = S.Solver(n, b, a, partitions=P, sizes=sizes, flags=pflags)
     sol.solve(dA, dB, XR, XL)
     sol.profile(True)
     for _ in range(args.profile_steps):
@@ -447,6 +458,13 @@ def main():
         achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
         roof = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=None)
+    elif dom_name == "fused":
+        # one workgroup per instance: FP64 vector multiply-adds on one CU
+        # per instance, against the chip's FP64 peak (and one CU's share)
+        achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 4), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 5), traffic=None,
+                    workgroups=1, frac_of_one_cu=round(achieved / (FP64_PEAK_TFLOPS / 256), 4))
     elif dom_name.startswith("inv_panel"):
         # Gauss-Jordan steps run on the FP64 vector units (pivot search and
         # row updates); bound by FP64 VALU issue and by the per-column latency
@@ -467,22 +485,22 @@ def main():
     log(f"[bench] P={P} per-solve kernel ms: {kernel_share}")
     sol.destroy()
 
-    def form_entry(q):
-        t = timed[q]
+    def form_entry(k):
+        t = timed[k]
         sec = t["elapsed"] / args.steps
-        return dict(partitions=q, solves_per_s=round(args.steps / t["elapsed"], 4),
+        return dict(partitions=t["P"], fused=bool(t["flags"]), solves_per_s=round(args.steps / t["elapsed"], 4),
                     ms_per_step=round(1e3 * sec, 3), launches=t["launches"],
                     pct_fp64_peak_executed=round(100 * t["ex"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
                     pct_fp64_peak_useful=round(100 * t["us"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
                     latency_ms=latency_summary(t["lat"]))
-    compare = {f"P{q}": form_entry(q) for q in forms + extra if q != P}
+    compare = {k: form_entry(k) for k, _, _ in variants if k != best}
 
     # the same form with the anti-Hermitian Sigma^< option (not the value: it
     # assumes the structure of the input), with its difference to the general path
     ah = None
     if args.antihermitian and sizes is None:
         XLg = XL.to_host()
-        solh = S.Solver(n, b, a, partitions=P, flags=args.flags | S.BT_SIGMA_ANTIHERMITIAN)
+        solh = S.Solver(n, b, a, partitions=P, flags=args.flags | pflags | S.BT_SIGMA_ANTIHERMITIAN)
         el_h, lat_h = time_solves(torch, solh, dA, dB, XR, XL, args.steps, args.warmup)
         ex_h, _ = S.flops(n, b, a, P, flags=S.BT_SIGMA_ANTIHERMITIAN)
         solh.destroy()
@@ -498,7 +516,7 @@ def main():
         log(f"[bench] P={P} with BT_SIGMA_ANTIHERMITIAN: {1e3 * sec:.2f} ms/solve, "
             f"X^< difference to the general path {ah['xl_rel_diff_vs_general']:.2e}")
         # restore the general path's outputs for the CPU-baseline comparison below
-        sol_g = S.Solver(n, b, a, partitions=P, flags=args.flags)
+        sol_g = S.Solver(n, b, a, partitions=P, flags=args.flags | pflags)
         sol_g.solve(dA, dB, XR, XL)
         sol_g.sync()
         sol_g.destroy()
@@ -531,7 +549,7 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": cfg.name, "n": n, "b": b if sizes is None else sizes, "a": a,
-                   "partitions": P,
+                   "partitions": P, "fused": bool(pflags),
                    "E": cfg.E, "eta": cfg.eta, "seed": cfg.seed, "hip_graph": bool(args.graph),
                    "tile_shapes": "autotuned" if args.tuned else "default rule"},
         "tflops_executed": round(tflops_ex, 3),

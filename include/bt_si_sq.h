@@ -110,6 +110,18 @@ typedef enum {
                                from the k-column ones the same way: about a sixth fewer
                                flops for BT.  The assertion is not checked; for other B
                                the result is wrong. */
+#define BT_FUSED 0x10u      /* small instances: one workgroup runs the instance's whole
+                               operation list (every product, diagonal-block inverse and
+                               block sum of the sweeps of Alg. 1/2, Sec. III-A and, for
+                               P > 1, Sec. III-B) in dependency order, with workgroup
+                               barriers only; a batch runs all its BT_FUSED instances in
+                               one launch, one workgroup each, beside the grouped launches
+                               of the others.  No launch per dependency level, so it pays
+                               where those levels are short (small b).  Needs every
+                               diagonal block and the tip of size <= 64 and BT_FP64
+                               without BT_PLAIN (else BT_ERR_INVALID).  Results agree with
+                               the grouped path to rounding (other summation order, and
+                               the inverse pivots on the rows of the block). */
 
 typedef struct {
     int32_t n;                  /* number of diagonal blocks, >= 1 */
@@ -272,7 +284,8 @@ typedef enum {
     BT_KERNEL_INV_FINISH = 4,     /* unused (kept for numbering) */
     BT_KERNEL_SUM = 5,            /* elementwise block sums */
     BT_KERNEL_NORM = 6,           /* block norms of the residual check */
-    BT_KERNEL_COUNT = 7
+    BT_KERNEL_FUSED = 7,          /* whole BT_FUSED instances, one workgroup each */
+    BT_KERNEL_COUNT = 8
 } bt_kernel_kind;
 
 typedef struct {

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libbtsisq.so")
 
 BT_OK, BT_ERR_INVALID, BT_ERR_OOM, BT_ERR_SINGULAR, BT_ERR_HIP, BT_ERR_STATE, BT_ERR_TOLERANCE = range(7)
 BT_FP64, BT_MIXED = 0, 1
-BT_DIAG_ONLY, BT_PLAIN, BT_GRAPH, BT_SIGMA_ANTIHERMITIAN = 0x1, 0x2, 0x4, 0x8
+BT_DIAG_ONLY, BT_PLAIN, BT_GRAPH, BT_SIGMA_ANTIHERMITIAN, BT_FUSED = 0x1, 0x2, 0x4, 0x8, 0x10
 STATUS_NAMES = {0: "BT_OK", 1: "BT_ERR_INVALID", 2: "BT_ERR_OOM", 3: "BT_ERR_SINGULAR",
                 4: "BT_ERR_HIP", 5: "BT_ERR_STATE", 6: "BT_ERR_TOLERANCE"}
 
@@ -32,7 +32,7 @@ EXPORTED = [
 ]
 
 KERNEL_NAMES = {0: "product_fp64", 1: "product_mixed", 2: "inv_panel", 3: "inv_init",
-                4: "inv_finish", 5: "sum", 6: "norm"}
+                4: "inv_finish", 5: "sum", 6: "norm", 7: "fused"}
 
 
 class bt_desc(C.Structure):

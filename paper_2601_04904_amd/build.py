@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbtsisq.so")
-SOURCES = ["gemm.hip", "inverse.hip", "elementwise.hip", "noalloc.hip", "plan.cpp"]
+SOURCES = ["gemm.hip", "inverse.hip", "elementwise.hip", "fused.hip", "noalloc.hip", "plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -103,6 +103,35 @@ struct NormJob {
     int32_t rows, cols;
 };
 
+// Fused small-instance path: one workgroup runs the whole operation list of
+// one instance.  A task is the instance's range of step records, in
+// dependency order; a record holds the step's kind and its descriptor
+// itself (fixed size), so the next step's record can be fetched while the
+// current one runs.
+constexpr int kFusedMaxDim = 64;    // largest diagonal block / tip the fused path inverts
+
+struct FusedInv {
+    const double2* src;   // d x d, row-major
+    double2* dst;         // d x d, row-major (may be src)
+    int32_t d;
+    int32_t tag;          // block id reported on a singular pivot
+};
+
+constexpr size_t kFusedBody = sizeof(GemmOp) > sizeof(AddOp) ? sizeof(GemmOp) : sizeof(AddOp);
+
+struct alignas(16) FusedRec {
+    int32_t type;         // 0 product, 1 inverse, 2 sum
+    int32_t pad[3];
+    alignas(16) unsigned char body[(kFusedBody + 15) / 16 * 16];   // a GemmOp, FusedInv or AddOp
+};
+static_assert(sizeof(FusedInv) <= kFusedBody, "record body too small");
+static_assert(sizeof(FusedRec) % 16 == 0, "records are 16-byte multiples");
+
+struct FusedTask {
+    int32_t first;        // first record
+    int32_t count;
+};
+
 // Device-side status: [0] error code (0 = ok, 3 = singular), [1] tag.
 struct DevStatus {
     int32_t code;

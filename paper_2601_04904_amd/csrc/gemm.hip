@@ -193,19 +193,21 @@ __device__ inline void issue_stage(const TermAddr<BM, BN>& ta, int k0, int tid, 
     constexpr int NA = BM * kBK / kThreads;
     constexpr int NB = BN * kBK / kThreads;
     const int lim = live ? ta.km1 - k0 : -1;   // largest k offset inside the term
-    const bool full = lim >= kBK - 1;
     // wave-uniform by construction; readfirstlane lets the compiler keep them in SGPRs
     const int soa = __builtin_amdgcn_readfirstlane(live ? k0 * ta.ska : 0);
     const int sob = __builtin_amdgcn_readfirstlane(live ? k0 * ta.skb : 0);
+    // A lane past k gets the top bit set: lim - p < 0 exactly then, and every
+    // in-range offset is below 2^31, so the result is at least kOOB.  Plain
+    // arithmetic rather than a choice, so the issue is straight-line code.
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-        const unsigned vo = full || a_p<BM>(ta.f.ah, tid + kThreads * q) <= lim ? ta.va[q] : kOOB;
-        st.ra[q] = load_b128(ta.ra, vo, soa);
+        const unsigned past = (unsigned)(lim - a_p<BM>(ta.f.ah, tid + kThreads * q)) & kOOB;
+        st.ra[q] = load_b128(ta.ra, ta.va[q] | past, soa);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const unsigned vo = full || b_p<BN>(ta.f.bh, tid + kThreads * q) <= lim ? ta.vb[q] : kOOB;
-        st.rb[q] = load_b128(ta.rb, vo, sob);
+        const unsigned past = (unsigned)(lim - b_p<BN>(ta.f.bh, tid + kThreads * q)) & kOOB;
+        st.rb[q] = load_b128(ta.rb, ta.vb[q] | past, sob);
     }
 }
 

@@ -53,6 +53,8 @@ hipError_t launch_inv_step(const InvJob* d_jobs, int njobs, int variant, int pan
                            DevStatus* status, hipStream_t s);
 hipError_t launch_add(const AddOp* d_ops, int nops, size_t max_elems, hipStream_t s);
 hipError_t launch_norms(const NormJob* d_jobs, int njobs, hipStream_t s);
+hipError_t launch_fused(const FusedTask* d_tasks, int ntasks, const FusedRec* d_recs, DevStatus* status,
+                        hipStream_t s);
 }  // namespace btsq
 
 namespace {
@@ -98,6 +100,7 @@ struct OpRec {
     int level = 0;
     int cls = 0;          // 1: critical A-chain stream, 0: main stream
     int wait_other = -1;  // highest level of a predecessor on the other stream
+    int task = -1;        // >= 0: run by workgroup `task` of the fused launch (BT_FUSED)
 };
 
 enum Mode { MODE_FACTOR = 0, MODE_SQ = 1, MODE_BOTH = 2 };
@@ -851,7 +854,7 @@ int levelize(std::vector<OpRec>& ops, bool plain = false) {
 }
 
 struct Launch {
-    int type;         // 0 gemm, 4 add, 5 norms, 6 inverse panel step
+    int type;         // 0 gemm, 4 add, 5 norms, 6 inverse panel step, 7 fused instances
     size_t off;       // element offset into the typed array
     int count;
     int tiles;        // gemm: total tiles
@@ -890,6 +893,8 @@ struct Program {
     std::vector<InvJob> inv;
     std::vector<AddOp> add;
     std::vector<NormJob> norm;
+    std::vector<FusedRec> frec;     // fused launch: step records and tasks
+    std::vector<FusedTask> ftask;
     std::vector<Launch> launches;
     size_t inv_scratch_bytes = 0;   // scratch the inverses need (max over levels)
     double flops = 0.0;
@@ -979,14 +984,90 @@ void assign_shape(Program& pg, Launch& L) {
     set_shape(pg, L, pick_shape(L.mixed, maxdim, t1));
 }
 
+AddOp make_add_op(const OpRec& o) {
+    AddOp a;
+    memset(&a, 0, sizeof a);
+    a.D = o.D.p;
+    a.nin = (int)o.ins.size();
+    a.rows = o.D.r;
+    a.cols = o.D.c;
+    for (int q = 0; q < a.nin; ++q) {
+        a.X[q] = o.ins[q].second.p;
+        a.c[q] = o.ins[q].first;
+    }
+    a.hmask = o.hmask;
+    return a;
+}
+
+// The operations of BT_FUSED instances (task >= 0): per task, its steps in
+// level order (each instance's operations were built in dependency order,
+// so a stable sort by level keeps every step after what it reads), and one
+// launch with a workgroup per task.  Returns false (pg.error set) for an
+// operation the fused kernel does not run.
+bool compile_fused(Program& pg, const std::vector<OpRec>& ops) {
+    int ntasks = 0;
+    for (const auto& o : ops) ntasks = std::max(ntasks, o.task + 1);
+    if (ntasks == 0) return true;
+    std::vector<std::vector<int>> bytask(ntasks);
+    for (int i = 0; i < (int)ops.size(); ++i)
+        if (ops[i].task >= 0) bytask[ops[i].task].push_back(i);
+    Launch L{};
+    L.type = 7;
+    L.off = 0;
+    L.count = ntasks;
+    L.cls = 0;
+    L.level = 0;
+    for (int t = 0; t < ntasks; ++t) {
+        auto& v = bytask[t];
+        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return ops[x].level < ops[y].level; });
+        FusedTask task{(int32_t)pg.frec.size(), (int32_t)v.size()};
+        for (int i : v) {
+            const OpRec& o = ops[i];
+            FusedRec rec;
+            memset(&rec, 0, sizeof rec);
+            if (o.kind == K_GEMM && !o.mixed) {
+                GemmOp g = make_gemm_op(o);
+                double f = 0, b = 0;
+                gemm_work(&g, 1, f, b);
+                L.flops += f;
+                L.bytes += b;
+                rec.type = 0;
+                memcpy(rec.body, &g, sizeof g);
+            } else if (o.kind == K_INV && o.D.r <= kFusedMaxDim) {
+                FusedInv j{o.C.p, o.D.p, o.D.r, o.tag};
+                L.flops += 8.0 * (double)j.d * j.d * j.d;
+                L.bytes += 32.0 * (double)j.d * j.d;
+                rec.type = 1;
+                memcpy(rec.body, &j, sizeof j);
+            } else if (o.kind == K_ADD && o.ins.size() <= (size_t)kMaxAdd) {
+                AddOp a = make_add_op(o);
+                L.flops += 8.0 * a.rows * a.cols * a.nin;
+                L.bytes += 16.0 * a.rows * a.cols * (a.nin + 1);
+                rec.type = 2;
+                memcpy(rec.body, &a, sizeof a);
+            } else {
+                pg.error = "internal: an operation of a BT_FUSED instance has no fused form";
+                return false;
+            }
+            pg.frec.push_back(rec);
+        }
+        pg.ftask.push_back(task);
+    }
+    pg.launches.push_back(L);
+    return true;
+}
+
 // Turn levelled operations into typed device arrays and a launch list.
-// Launches are ordered by level and, within a level, critical stream first.
+// Launches are ordered by level and, within a level, critical stream first;
+// the fused launch (BT_FUSED instances) comes first, on the main stream.
 // inv_pool: base of the inverse scratch pool (may be fake in dry runs).
 Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
     Program pg;
     pg.levels = nlevels;
+    if (!compile_fused(pg, ops)) return pg;
     std::vector<std::vector<int>> bylevel(nlevels);
-    for (int i = 0; i < (int)ops.size(); ++i) bylevel[ops[i].level].push_back(i);
+    for (int i = 0; i < (int)ops.size(); ++i)
+        if (ops[i].task < 0) bylevel[ops[i].level].push_back(i);
     auto mk = [&](int type, size_t off, int count, int tiles, int mixed, int maxd, int panel,
                   size_t maxe, int cls, int level, int wait) {
         Launch L{type, off, count, tiles, mixed, maxd, panel, maxe};
@@ -1078,17 +1159,7 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
                         pg.error = "internal: a block sum has more than 17 inputs";
                         return pg;
                     }
-                    AddOp a;
-                    memset(&a, 0, sizeof a);
-                    a.D = o.D.p;
-                    a.nin = (int)o.ins.size();
-                    a.rows = o.D.r;
-                    a.cols = o.D.c;
-                    for (int q = 0; q < a.nin; ++q) {
-                        a.X[q] = o.ins[q].second.p;
-                        a.c[q] = o.ins[q].first;
-                    }
-                    a.hmask = o.hmask;
+                    AddOp a = make_add_op(o);
                     maxe = std::max(maxe, (size_t)a.rows * a.cols);
                     pg.add.push_back(a);
                     aw = std::max(aw, o.wait_other);
@@ -1122,6 +1193,7 @@ Program compile(std::vector<OpRec>& ops, int nlevels, char* inv_pool) {
         for (int c = 0; c < 2; ++c) last_of_level[c].assign(nlevels, -1);
         for (int i = 0; i < (int)pg.launches.size(); ++i) {
             const Launch& L = pg.launches[i];
+            if (L.type == 7) continue;     // independent of every other launch
             last_of_level[L.cls][L.level] = i;
         }
         for (int c = 0; c < 2; ++c)
@@ -1209,6 +1281,7 @@ struct bt_si_sq_plan {
         bool dev_own = false;             // dev allocated on its own (did not fit the arena)
         std::vector<char> host;           // host copy the upload reads (kept as long as dev)
         size_t off_gemm = 0, off_inv = 0, off_add = 0, off_norm = 0;
+        size_t off_frec = 0, off_ftask = 0;
         std::vector<hipEvent_t> events;   // cross-stream events of the launch list
         hipGraphExec_t graph = nullptr;   // the launch list captured as a graph (BT_GRAPH)
     };
@@ -1263,6 +1336,22 @@ bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
         msg = "BT_DIAG_ONLY needs BT_FP64: the mixed path's error estimate reads the off-diagonal blocks";
         return false;
     }
+    if (d->flags & BT_FUSED) {
+        int mx = d->a;
+        if (d->block_sizes) {
+            for (int i = 0; i < d->n; ++i) mx = std::max(mx, (int)d->block_sizes[i]);
+        } else {
+            mx = std::max(mx, (int)d->b);
+        }
+        if (mx > kFusedMaxDim) {
+            msg = "BT_FUSED needs every diagonal block and the arrow tip of size at most 64";
+            return false;
+        }
+        if (d->precision != BT_FP64 || (d->flags & BT_PLAIN)) {
+            msg = "BT_FUSED needs BT_FP64 and no BT_PLAIN";
+            return false;
+        }
+    }
     const int P = d->partitions;
     if (P < 1) { msg = "partitions must be >= 1"; return false; }
     Dims D(d->n, d->b, d->a, d->block_sizes);
@@ -1287,6 +1376,7 @@ struct Built {
     std::vector<OpRec> ops;
     std::vector<double*> norm_out;
     double flops = 0;
+    int fused_tasks = 0;
 };
 
 bool build_instances(std::vector<Instance>& inst, const std::vector<int>& sel, Mode mode,
@@ -1327,7 +1417,11 @@ bool build_instances(std::vector<Instance>& inst, const std::vector<int>& sel, M
         }
         out.flops += bd.flops;
         out.norm_out.push_back(bd.check && bd.emitB() ? reinterpret_cast<double*>(bd.norm_out.p) : nullptr);
-        for (auto& o : bd.ops) out.ops.push_back(std::move(o));
+        const int task = (I.desc.flags & BT_FUSED) ? out.fused_tasks++ : -1;
+        for (auto& o : bd.ops) {
+            o.task = task;
+            out.ops.push_back(std::move(o));
+        }
     }
     if (dry_total) *dry_total = run;
     return true;
@@ -1362,6 +1456,7 @@ int kernel_kind(const Launch& L) {
         case 0: return L.mixed ? BT_KERNEL_PRODUCT_MIXED : BT_KERNEL_PRODUCT_FP64;
         case 5: return BT_KERNEL_NORM;
         case 6: return BT_KERNEL_INV_PANEL;
+        case 7: return BT_KERNEL_FUSED;
         default: return BT_KERNEL_SUM;
     }
 }
@@ -1434,6 +1529,10 @@ hipError_t enqueue_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, hipStream
             case 4: e = launch_add(da + L.off, L.count, L.maxelems, s); break;
             case 5: e = launch_norms(dn + L.off, L.count, s); break;
             case 6: e = launch_inv_step(dj + L.off, L.count, L.maxd, L.panel, L.tiles, h->status, s); break;
+            case 7:
+                e = launch_fused(reinterpret_cast<const FusedTask*>(c.dev + c.off_ftask) + L.off, L.count,
+                                 reinterpret_cast<const FusedRec*>(c.dev + c.off_frec), h->status, s);
+                break;
         }
         if (e != hipSuccess) return e;
         if (h->profiling && ea && eb) {
@@ -1472,13 +1571,21 @@ std::vector<uint64_t> make_key(Mode mode, bool fp64_rerun, const std::vector<int
 
 // Device bytes of a compiled program's operation lists (each array starting
 // on a 256-byte boundary, as prepare_and_run lays them out).
-size_t program_bytes(const Program& pg) {
-    const size_t bg = pg.gemm.size() * sizeof(GemmOp);
-    const size_t bi = pg.inv.size() * sizeof(InvJob);
-    const size_t ba = pg.add.size() * sizeof(AddOp);
-    const size_t bn = pg.norm.size() * sizeof(NormJob);
-    return align256(align256(align256(bg) + bi) + ba) + bn + 256;
+struct ProgLayout {
+    size_t off_inv, off_add, off_norm, off_frec, off_ftask, total;
+};
+ProgLayout program_layout(const Program& pg) {
+    ProgLayout L;
+    L.off_inv = align256(pg.gemm.size() * sizeof(GemmOp));
+    L.off_add = align256(L.off_inv + pg.inv.size() * sizeof(InvJob));
+    L.off_norm = align256(L.off_add + pg.add.size() * sizeof(AddOp));
+    L.off_frec = align256(L.off_norm + pg.norm.size() * sizeof(NormJob));
+    L.off_ftask = align256(L.off_frec + pg.frec.size() * sizeof(FusedRec));
+    L.total = L.off_ftask + pg.ftask.size() * sizeof(FusedTask) + 256;
+    return L;
 }
+
+size_t program_bytes(const Program& pg) { return program_layout(pg).total; }
 
 // Layout of a handle's device block (see bt_si_sq_plan): workspace, inverse
 // scratch, status word, then room for kArenaPrograms operation lists the size
@@ -1537,14 +1644,8 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& s
         if (pg.inv_scratch_bytes > h->inv_bytes)
             return set_err(h, BT_ERR_INVALID, "internal: inverse scratch too small");
         pg.flops = bt.flops;
-        const size_t bg = pg.gemm.size() * sizeof(GemmOp);
-        const size_t bi = pg.inv.size() * sizeof(InvJob);
-        const size_t ba = pg.add.size() * sizeof(AddOp);
-        const size_t bn = pg.norm.size() * sizeof(NormJob);
-        const size_t off_inv = (bg + 255) & ~(size_t)255;
-        const size_t off_add = (off_inv + bi + 255) & ~(size_t)255;
-        const size_t off_norm = (off_add + ba + 255) & ~(size_t)255;
-        const size_t total = off_norm + bn + 256;
+        const ProgLayout PL = program_layout(pg);
+        const size_t total = PL.total;
         // Device room for the lists: the handle's arena, taken in order; when
         // it is full every cached program is dropped (after its streams are
         // idle) and the arena starts over.  A list larger than the whole
@@ -1580,10 +1681,13 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& s
         c->dev_bytes = total;
         c->host.assign(total, 0);
         char* stage = c->host.data();
-        if (bg) memcpy(stage, pg.gemm.data(), bg);
-        if (bi) memcpy(stage + off_inv, pg.inv.data(), bi);
-        if (ba) memcpy(stage + off_add, pg.add.data(), ba);
-        if (bn) memcpy(stage + off_norm, pg.norm.data(), bn);
+        auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) memcpy(stage + off, src, bytes); };
+        put(0, pg.gemm.data(), pg.gemm.size() * sizeof(GemmOp));
+        put(PL.off_inv, pg.inv.data(), pg.inv.size() * sizeof(InvJob));
+        put(PL.off_add, pg.add.data(), pg.add.size() * sizeof(AddOp));
+        put(PL.off_norm, pg.norm.data(), pg.norm.size() * sizeof(NormJob));
+        put(PL.off_frec, pg.frec.data(), pg.frec.size() * sizeof(FusedRec));
+        put(PL.off_ftask, pg.ftask.data(), pg.ftask.size() * sizeof(FusedTask));
         e = hipMemcpyAsync(c->dev, stage, total, hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) return hip_err(h, e, "hipMemcpyAsync(op list)");
         e = hipEventRecord(h->upload_done, h->stream);
@@ -1598,9 +1702,11 @@ bt_status prepare_and_run(bt_si_sq_plan* h, Mode mode, const std::vector<int>& s
         c->norm_out = bt.norm_out;
         c->sel = sel;
         c->off_gemm = 0;
-        c->off_inv = off_inv;
-        c->off_add = off_add;
-        c->off_norm = off_norm;
+        c->off_inv = PL.off_inv;
+        c->off_add = PL.off_add;
+        c->off_norm = PL.off_norm;
+        c->off_frec = PL.off_frec;
+        c->off_ftask = PL.off_ftask;
         c->key = key;
     }
     c->stamp = ++h->clock;

@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (BT_DIAG_ONLY, BT_FP64, BT_GRAPH, BT_MIXED, BT_PLAIN, BT_SIGMA_ANTIHERMITIAN, BTError,
+from ._lib import (BT_DIAG_ONLY, BT_FP64, BT_FUSED, BT_GRAPH, BT_MIXED, BT_PLAIN, BT_SIGMA_ANTIHERMITIAN, BTError,
                    BTToleranceError, check, check_tol, make_desc)
 
 FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
@@ -173,7 +173,9 @@ class Solver:
 
     flags: BT_PLAIN (reference schedule), BT_GRAPH (launch lists replayed as
     HIP graphs), BT_SIGMA_ANTIHERMITIAN (Sigma^< anti-Hermitian, asserted by
-    the caller and not checked; fewer X^< products).
+    the caller and not checked; fewer X^< products), BT_DIAG_ONLY (diagonal
+    blocks only), BT_FUSED (blocks and tip <= 64: the whole solve in one
+    workgroup, one launch).
     """
 
     def __init__(self, n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, tol=1e-4,
@@ -335,7 +337,7 @@ def batch_workspace_bytes(specs) -> int:
 
 __all__ = ["DeviceBlocks", "VarDeviceBlocks", "Solver", "BatchSolver", "workspace_bytes", "batch_workspace_bytes",
            "partition_bounds", "flops", "BT_FP64", "BT_MIXED", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN",
-           "BT_DIAG_ONLY", "BTError", "BTToleranceError",
+           "BT_DIAG_ONLY", "BT_FUSED", "BTError", "BTToleranceError",
            "autotune", "tune_table", "set_tune_table"]
 
 

@@ -190,7 +190,7 @@ def test_header_flag_values_match_binding():
     with open(os.path.join(root, "include", "bt_si_sq.h")) as f:
         text = f.read()
     flags = dict(re.findall(r"#define (BT_[A-Z_]+) (0x[0-9a-f]+)u", text))
-    assert set(flags) == {"BT_DIAG_ONLY", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN"}
+    assert set(flags) == {"BT_DIAG_ONLY", "BT_PLAIN", "BT_GRAPH", "BT_SIGMA_ANTIHERMITIAN", "BT_FUSED"}
     for name, val in flags.items():
         assert getattr(_lib, name) == int(val, 16), name
     nums = dict(re.findall(r"#define (BT_TILE_SHAPES|BT_TUNE_SIZE_CLASSES|BT_TUNE_WORK_CLASSES) (\d+)", text))
@@ -277,6 +277,26 @@ def test_diag_only_flop_model_and_mixed_rejection():
     d = LB.make_desc(8, 16, 0, 1, None, precision=LB.BT_MIXED, flags=LB.BT_DIAG_ONLY)
     assert L.bt_si_sq_workspace_bytes(C.byref(d)) == 0
     assert b"BT_DIAG_ONLY" in L.bt_si_sq_last_error(None)
+
+
+def test_fused_flag_limits():
+    """BT_FUSED: every diagonal block and the tip at most 64, FP64, no
+    BT_PLAIN."""
+    from paper_2601_04904_amd import _lib as LB
+    L = _lib.lib()
+    ok = [LB.make_desc(16, 32, 0, 1, None, flags=LB.BT_FUSED),
+          LB.make_desc(9, 64, 64, 3, None, flags=LB.BT_FUSED | LB.BT_DIAG_ONLY),
+          LB.make_desc(5, 0, 16, 1, None, flags=LB.BT_FUSED, sizes=[8, 64, 3, 40, 1])]
+    for d in ok:
+        assert L.bt_si_sq_workspace_bytes(C.byref(d)) > 0, L.bt_si_sq_last_error(None)
+    bad = [LB.make_desc(16, 65, 0, 1, None, flags=LB.BT_FUSED),
+           LB.make_desc(16, 32, 65, 1, None, flags=LB.BT_FUSED),
+           LB.make_desc(4, 0, 0, 1, None, flags=LB.BT_FUSED, sizes=[8, 65, 3, 4]),
+           LB.make_desc(16, 32, 0, 1, None, precision=LB.BT_MIXED, flags=LB.BT_FUSED),
+           LB.make_desc(16, 32, 0, 1, None, flags=LB.BT_FUSED | LB.BT_PLAIN)]
+    for d in bad:
+        assert L.bt_si_sq_workspace_bytes(C.byref(d)) == 0
+        assert b"BT_FUSED" in L.bt_si_sq_last_error(None)
 
 
 def test_block_sizes_descriptor():

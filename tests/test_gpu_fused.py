@@ -1,0 +1,202 @@
+"""BT_FUSED: whole solves of small instances in one workgroup each, through
+the C ABI, against the oracle (FP64 bar 1e-11 per selected block, rel_err in
+tests/_util.py).  Covers sequential and partitioned forms with and without
+arrowhead, the small-block workload (n=16, b=32, seed 0) against the dense
+definition, diagonal-only outputs, blocks of different sizes, the factor /
+selected-solve split, batches that mix fused and grouped instances, graph
+replays and a singular block.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_04904_amd.synth import CONFIGS, gen_problem, gen_problem_var, config_problem
+from tests._util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+FIELDS = ("diag", "upper", "lower", "arrow_right", "arrow_bottom", "tip")
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2601_04904_amd import solver
+    return solver
+
+
+def run(S, A, B, P=1, bounds=None, flags=0, split=False):
+    n, b, a = A.diag.shape[0], A.diag.shape[1], A.tip.shape[0]
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    sol = S.Solver(n, b, a, partitions=P, bounds=bounds, flags=S.BT_FUSED | flags)
+    if split:
+        sol.factor(dA, XR)
+        sol.selected_solve(dB, XL)
+    else:
+        sol.solve(dA, dB, XR, XL)
+    sol.sync()
+    launches = sol.last_launch_count()
+    out = XR.to_host(), XL.to_host()
+    sol.destroy()
+    return out, launches
+
+
+CASES = [
+    # n, b, a, partitions, bounds
+    (1, 5, 0, 1, None),
+    (2, 3, 0, 1, None),
+    (16, 32, 0, 1, None),
+    (16, 32, 0, 2, None),
+    (9, 37, 0, 3, [0, 3, 6, 9]),
+    (12, 64, 0, 1, None),
+    (7, 40, 19, 1, None),
+    (12, 24, 20, 3, None),
+    (10, 33, 64, 4, [0, 2, 4, 6, 10]),
+    (6, 64, 64, 2, [0, 1, 6]),
+    (24, 16, 0, 9, None),
+    (1, 20, 7, 1, None),
+]
+
+
+@pytest.mark.parametrize("n,b,a,P,bounds", CASES)
+def test_fused_parity(S, n, b, a, P, bounds):
+    print(f"case BT_FUSED n={n} b={b} a={a} P={P} bounds={bounds}", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-3, seed=70 + n + b + a + P)
+    R0, L0 = oracle.solve_dense(A, B)
+    (XR, XL), launches = run(S, A, B, P, bounds)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    print(f"  err R={eR:.3e} L={eL:.3e} launches={launches}", flush=True)
+    assert eR < TOL and eL < TOL
+    assert launches == 1
+
+
+def test_small_block_workload_sequential(S):
+    """n=16, b=32, E=0.3, eta=1e-3, seed 0, sequential: one launch, against
+    the dense definition of the selected blocks."""
+    print("case BT_FUSED bt_n16_b32 seed 0 P=1", flush=True)
+    cfg = CONFIGS["bt_n16_b32"]
+    assert (cfg.n, cfg.b, cfg.a, cfg.E, cfg.eta, cfg.seed) == (16, 32, 0, 0.3, 1e-3, 0)
+    A, B = config_problem("bt_n16_b32")
+    R0, L0 = oracle.solve_dense(A, B)
+    (XR, XL), launches = run(S, A, B, 1)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    print(f"  err R={eR:.3e} L={eL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL and launches == 1
+
+
+@pytest.mark.parametrize("n,b,a,P", [(10, 32, 0, 1), (9, 24, 16, 3)])
+def test_fused_split_and_diag_only(S, n, b, a, P):
+    print(f"case BT_FUSED split / diag-only n={n} b={b} a={a} P={P}", flush=True)
+    # E = 0.3: the oracle's own partitioned sweep is within 1e-13 of the dense
+    # definition on these inputs (at E = -0.2 the P = 3 ordering itself loses
+    # accuracy, to 3e-10 on X^<, whatever executes it)
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-3, seed=90 + n)
+    R0, L0 = oracle.solve_dense(A, B)
+    (XR, XL), _ = run(S, A, B, P, split=True)
+    assert rel_err(XR, R0) < TOL and rel_err(XL, L0) < TOL
+    (DR, DL), _ = run(S, A, B, P, flags=S.BT_DIAG_ONLY)
+    for X, Ref in ((DR, R0), (DL, L0)):
+        for i in range(n):
+            assert np.linalg.norm(X.diag[i] - Ref.diag[i]) < TOL * np.linalg.norm(Ref.diag[i])
+        if a:
+            assert np.linalg.norm(X.tip - Ref.tip) < TOL * np.linalg.norm(Ref.tip)
+
+
+def test_fused_block_sizes(S):
+    sizes, a = [8, 64, 3, 40, 17, 29], 12
+    print(f"case BT_FUSED sizes={sizes} a={a}", flush=True)
+    A, B = gen_problem_var(sizes, a, E=0.3, eta=1e-3, seed=5)
+    R0, L0 = oracle.solve_dense(A, B)
+    dA, dB = S.VarDeviceBlocks.from_host(A), S.VarDeviceBlocks.from_host(B)
+    XR, XL = S.VarDeviceBlocks.empty(sizes, a), S.VarDeviceBlocks.empty(sizes, a)
+    sol = S.Solver(len(sizes), 0, a, partitions=2, sizes=sizes, flags=S.BT_FUSED)
+    sol.solve(dA, dB, XR, XL)
+    sol.sync()
+    eR, eL = rel_err(XR.to_host(), R0), rel_err(XL.to_host(), L0)
+    sol.destroy()
+    print(f"  err R={eR:.3e} L={eL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL
+
+
+def test_batch_mixes_fused_and_grouped_instances(S):
+    """Fused instances match the oracle; the grouped instances of the same
+    batch are bitwise what they are alone (the fused launch shares nothing
+    with them)."""
+    specs = [dict(n=9, b=64, a=0, flags=S.BT_FUSED), dict(n=14, b=32, a=16, partitions=2),
+             dict(n=5, b=20, a=7, flags=S.BT_FUSED), dict(n=12, b=48, a=0, partitions=3),
+             dict(n=16, b=32, a=0, flags=S.BT_FUSED)]
+    print("case BT_FUSED batch", specs, flush=True)
+    probs = [gen_problem(sp["n"], sp["b"], sp["a"], E=0.1 * i, eta=1e-3, seed=200 + i) for i, sp in enumerate(specs)]
+
+    def solve(sps, prs):
+        dA = [S.DeviceBlocks.from_host(A) for A, _ in prs]
+        dB = [S.DeviceBlocks.from_host(B) for _, B in prs]
+        XR = [S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]) for sp in sps]
+        XL = [S.DeviceBlocks.empty(sp["n"], sp["b"], sp["a"]) for sp in sps]
+        bs = S.BatchSolver(sps)
+        bs.solve(dA, dB, XR, XL)
+        bs.sync()
+        out = [(x.to_host(), y.to_host()) for x, y in zip(XR, XL)]
+        bs.destroy()
+        return out
+
+    out = solve(specs, probs)
+    for sp, (A, B), (XR, XL) in zip(specs, probs, out):
+        R0, L0 = oracle.solve_dense(A, B)
+        eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+        print(" ", sp, f"R={eR:.2e} L={eL:.2e}", flush=True)
+        assert eR < TOL and eL < TOL
+    for i in (1, 3):
+        alone = solve([specs[i]], [probs[i]])[0]
+        for f in FIELDS:
+            assert np.array_equal(getattr(alone[0], f), getattr(out[i][0], f))
+            assert np.array_equal(getattr(alone[1], f), getattr(out[i][1], f))
+
+
+def test_fused_graph_replays_match_eager(S):
+    import torch
+    n, b, a = 12, 32, 16
+    print("case BT_FUSED | BT_GRAPH replays", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=1e-3, seed=11)
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    eager = S.Solver(n, b, a, partitions=2, flags=S.BT_FUSED)
+    eager.solve(dA, dB, XR, XL)
+    eager.sync()
+    ref = XR.to_host(), XL.to_host()
+    eager.destroy()
+    sol = S.Solver(n, b, a, partitions=2, flags=S.BT_FUSED | S.BT_GRAPH)
+    junk = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        for X in (XR, XL):
+            X.diag.zero_()
+        sol.solve(dA, dB, XR, XL)
+        junk.mul_(1.0001)
+        sol.sync()
+        got = XR.to_host(), XL.to_host()
+        for f in FIELDS:
+            assert np.array_equal(getattr(got[0], f), getattr(ref[0], f)), f"replay {rep}"
+            assert np.array_equal(getattr(got[1], f), getattr(ref[1], f)), f"replay {rep}"
+    sol.destroy()
+
+
+def test_fused_singular_block_reported(S):
+    from paper_2601_04904_amd._lib import BTError, BT_ERR_SINGULAR
+    n, b = 4, 16
+    print("case BT_FUSED singular block", flush=True)
+    A, B = gen_problem(n, b, 0, seed=1)
+    A.diag[0][:, 3] = 0.0
+    A.upper[0][:, :] = 0.0
+    A.lower[0][:, :] = 0.0
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, 0), S.DeviceBlocks.empty(n, b, 0)
+    sol = S.Solver(n, b, 0, flags=S.BT_FUSED)
+    sol.solve(dA, dB, XR, XL)
+    with pytest.raises(BTError) as ei:
+        sol.sync()
+    assert ei.value.status == BT_ERR_SINGULAR
+    assert "block 0" in str(ei.value)
+    sol.destroy()
