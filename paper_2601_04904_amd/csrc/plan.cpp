@@ -566,7 +566,10 @@ struct Builder {
         const int dk = D.dim(k);
         const auto& N = r.N;
         const double2 one = cplx(1), mone = cplx(-1), zero = cplx(0);
-        // selected inversion
+        // selected inversion, on the critical stream: the A-chain is done by
+        // now, so the X^R sweep runs ahead on it while the main stream
+        // follows with the X^< products that read each step's X^R
+        cur_cls = 1;
         for (int v : N) {
             r.tau[v] = alloc(dk, D.dim(v));
             gemm(emitA(), r.tau[v], MatRef{}, zero, {{r.S, false, r.Akv[v], false, one}}, mx);
@@ -594,6 +597,7 @@ struct Builder {
             gemm(emitA(), xloc(false, k, k), r.S, one, ts, mx);
         }
         // selected quadratic solve
+        cur_cls = 0;
         for (int u : N) {
             r.GB[u] = alloc(D.dim(u), dk);
             std::vector<TermSpec> ts;
