@@ -410,7 +410,12 @@ def main():
     # the forms the workload names (e.g. sequential and P=8); the value is the
     # fastest of them, the others are reported beside it
     forms = [args.partitions] if args.partitions is not None else list(cfg.partitions)
-    extra = [q for q in (args.compare_partitions or []) if q not in forms]
+    # by default the two-partition form is timed beside the named ones where the
+    # workload names both the sequential and a many-partition form: on one GPU
+    # it is the fastest (no middle partitions, no fill), reported, not the value
+    default_extra = [2] if args.partitions is None and 1 in forms and max(forms) > 2 else []
+    extra = [q for q in (args.compare_partitions if args.compare_partitions is not None else default_extra)
+             if q not in forms]
     log(f"[bench] workload {cfg.name}: n={n} b={b if sizes is None else 'per block'} a={a} "
         f"forms P={forms} extra P={extra} eta={cfg.eta}")
     t0 = time.perf_counter()
