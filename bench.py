@@ -74,7 +74,9 @@ def time_solves(torch, sol, dA, dB, XR, XL, steps, warmup):
 def measured_traffic(kernel, workload, partitions):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
     against a plain copy) as last measured with rocprofv3 counters, or None if
-    there is no measurement for this workload or the kernel source changed since."""
+    there is no measurement for this workload or a source it depends on (the
+    kernel, and the scheduler that decides what each launch holds) changed
+    since."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -82,9 +84,10 @@ def measured_traffic(kernel, workload, partitions):
             rec = json.load(f).get(kernel)
         if not rec or rec["workload"] != workload or rec["partitions"] != partitions:
             return None
-        with open(os.path.join(root, rec["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-                return None
+        for src, digest in rec["sources_sha256"].items():
+            with open(os.path.join(root, src), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
         return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         return None
@@ -446,7 +449,9 @@ def main():
     ms = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel of the reported form, from HIP events
-    # recorded around each launch on the stream it runs on
+    # recorded around each launch; while profiling the library runs the
+    # launches one after another on one stream, so each event pair times the
+    # kernel alone (in the timed solves the two streams' launches overlap)
     sol = S.Solver(n, b, a, partitions=P, sizes=sizes, flags=pflags)
     sol.solve(dA, dB, XR, XL)
     sol.profile(True)

@@ -270,7 +270,10 @@ int32_t bt_si_sq_last_launch_count(bt_si_sq_handle h);
 
 /* Per-kernel measurement.  With enable != 0 every launch of the following
  * factor/selected_solve/solve calls is bracketed by HIP events recorded on
- * the handle's stream, and bt_si_sq_profile_stats returns, per kernel
+ * the handle's stream (all launches then run on that stream, one after
+ * another, so each launch's event time is the kernel's own time rather
+ * than its share of a GPU that other streams' launches also use), and
+ * bt_si_sq_profile_stats returns, per kernel
  * family, the launch count, the summed event time and the summed
  * algorithmic work of those launches.  Enabling (or disabling) clears the
  * totals.  Event bracketing adds host work per launch; time whole solves

@@ -1517,7 +1517,9 @@ hipError_t enqueue_program(bt_si_sq_plan* h, bt_si_sq_plan::Cached& c, hipStream
     if (e == hipSuccess) e = hipStreamWaitEvent(h->astream, h->ev_start, 0);
     if (e != hipSuccess) return e;
     for (const Launch& L : pg.launches) {
-        hipStream_t s = L.cls ? h->astream : main;
+        // profiling runs every launch on the main stream, one after another,
+        // so that each launch's events time the kernel alone
+        hipStream_t s = (L.cls && !h->profiling) ? h->astream : main;
         if (L.wait_event >= 0) {
             e = hipStreamWaitEvent(s, c.events[L.wait_event], 0);
             if (e != hipSuccess) return e;
