@@ -47,9 +47,11 @@ template <class T> __device__ inline T* uni(T* p) {
 #ifdef __HIP_DEVICE_COMPILE__
 typedef const __attribute__((address_space(1))) double2* gcp;
 typedef __attribute__((address_space(1))) double2* gp;
+typedef __attribute__((address_space(1))) double* gdp;
 #else
 typedef const double2* gcp;
 typedef double2* gp;
+typedef double* gdp;
 #endif
 
 // One product term with its fields in scalar registers.
@@ -76,12 +78,9 @@ __device__ inline FTerm load_term(const GemmTerm& T) {
 
 // ---------------------------------------------------------------------------
 // Products D = beta C + sum_t alpha_t op(A_t) op(B_t), by the whole
-// workgroup: TM x TM output tiles in turn; the threads form a 16 x 16 grid,
-// each owning the (TM/16) x (TM/16) outputs at its grid position plus
-// multiples of 16, so a wave reads 16 consecutive B entries and 4 A entries
-// (broadcast) from LDS per k.  Operands pass through LDS kFK values of k at
-// a time; the next stage's global loads are issued before the current
-// stage's multiply-adds.
+// workgroup: TM x TM output tiles in turn.  Operands pass through LDS kFK
+// values of k at a time; the next stage's global loads are issued before the
+// current stage's multiply-adds.
 template <int TM>
 struct FStage {
     static constexpr int NL = TM * kFK / kFT;
@@ -138,9 +137,18 @@ __device__ inline void fgemm_store(const FTerm& T, int tid, const FStage<TM>& st
     }
 }
 
+// The multiply-adds run on the FP64 matrix cores with the grouped kernel's
+// scheme: the complex product as the real product of A' (A read as m x 2k
+// real) and B'' (B expanded to 2k x 2n real, [[Re, Im], [-Im, Re]] per
+// entry), v_mfma_f64_4x4x4f64 used as a 4-row x 16-column x 4-k product
+// with A replicated over its four blocks (A[l%4][l/16], B[l/16][l%16],
+// D[l/16][l%16]).  The four waves split the TM x TM tile 2 x 2: each owns
+// TM/2 rows (TM/8 groups of 4) and TM/2 complex columns (TM/16 blocks of 16
+// real columns).
 template <int TM>
 __device__ void fused_gemm(const GemmOp& op, double2* lds, int tid) {
-    constexpr int RT = TM / 16;
+    constexpr int RG = TM / 8;                // 4-row groups per wave
+    constexpr int NI = TM / 16;               // 16-real-column blocks per wave
     double2* As = lds;
     double2* Bs = lds + kFK * kFLd<TM>;
     const int m = uni(op.m), n = uni(op.n), nt = uni(op.nterms);
@@ -148,16 +156,22 @@ __device__ void fused_gemm(const GemmOp& op, double2* lds, int tid) {
     gcp C = (gcp)uni(op.C);
     const int ldd = uni(op.ldd), ldc = uni(op.ldc);
     const double2 beta = uni(op.beta);
-    const int ty = tid >> 4, tx = tid & 15;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int cA = (lane >> 4) & 1;           // real k within the pair: 0 = Re of A, 1 = Im
+    const int pOff = lane >> 5;               // complex k offset within the 4-wide real k step
+    const int r16 = lane & 15;
+    const int d = lane & 1;                   // output component of this lane's B'' column
+    const unsigned long long negB = (cA == 1 && d == 0) ? 0x8000000000000000ull : 0ull;
     const int tn = (n + TM - 1) / TM;
     const int tiles = ((m + TM - 1) / TM) * tn;
     for (int t = 0; t < tiles; ++t) {
         const int i0 = (t / tn) * TM, j0 = (t % tn) * TM;
-        double2 acc[RT][RT];
+        double acc[RG][NI];
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int c = 0; c < RT; ++c) acc[r][c] = make_double2(0.0, 0.0);
+            for (int ni = 0; ni < NI; ++ni) acc[g][ni] = 0.0;
         // stages are (term, k offset) pairs in order, empty terms skipped
         int s = 0, k0 = 0;
         while (s < nt && uni(op.t[s].k) <= 0) ++s;
@@ -180,31 +194,43 @@ __device__ void fused_gemm(const GemmOp& op, double2* lds, int tid) {
             }
             // entries past k are zero in both operands: the full depth is exact
 #pragma unroll
-            for (int kk = 0; kk < kFK; ++kk) {
-                double2 a[RT], b[RT];
+            for (int kk = 0; kk < kFK / 2; ++kk) {
+                const int p = 2 * kk + pOff;
+                double av[RG], bv[NI];
 #pragma unroll
-                for (int r = 0; r < RT; ++r) a[r] = As[kk * kFLd<TM> + ty + 16 * r];
+                for (int g = 0; g < RG; ++g)
+                    av[g] = reinterpret_cast<const double*>(&As[p * kFLd<TM> + wm * (TM / 2) + g * 4 + (lane & 3)])[cA];
 #pragma unroll
-                for (int c = 0; c < RT; ++c) b[c] = Bs[kk * kFLd<TM> + tx + 16 * c];
+                for (int ni = 0; ni < NI; ++ni) {
+                    const double v = reinterpret_cast<const double*>(&Bs[p * kFLd<TM> + ((wn * TM + ni * 16 + r16) >> 1)])[cA ^ d];
+                    bv[ni] = __longlong_as_double(__double_as_longlong(v) ^ (long long)negB);
+                }
 #pragma unroll
-                for (int r = 0; r < RT; ++r)
+                for (int g = 0; g < RG; ++g)
 #pragma unroll
-                    for (int c = 0; c < RT; ++c) cfma(acc[r][c], a[r], b[c]);
+                    for (int ni = 0; ni < NI; ++ni)
+                        acc[g][ni] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[g], bv[ni], acc[g][ni], 0, 0, 0);
             }
             s = s2;
             k0 = k2;
             cur = nxt;
         }
-        // C may be D: each output is read and written by the same thread
+        // lane: component d of complex column (wn TM + ni 16 + r16) / 2 of row
+        // group g's row lane / 16; C may be D: each output element is read
+        // and written by the same lane
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int c = 0; c < RT; ++c) {
-                const int gi = i0 + ty + 16 * r, gj = j0 + tx + 16 * c;
+            for (int ni = 0; ni < NI; ++ni) {
+                const int gi = i0 + wm * (TM / 2) + g * 4 + (lane >> 4);
+                const int gj = j0 + ((wn * TM + ni * 16 + r16) >> 1);
                 if (gi < m && gj < n) {
-                    double2 v = acc[r][c];
-                    if (C) cfma(v, beta, C[(size_t)gi * ldc + gj]);
-                    D[(size_t)gi * ldd + gj] = v;
+                    double v = acc[g][ni];
+                    if (C) {
+                        const double2 c = C[(size_t)gi * ldc + gj];
+                        v += d ? (beta.x * c.y + beta.y * c.x) : (beta.x * c.x - beta.y * c.y);
+                    }
+                    reinterpret_cast<gdp>(D + (size_t)gi * ldd + gj)[d] = v;
                 }
             }
     }
