@@ -220,7 +220,7 @@ def bench_batch(args, torch, S):
     fp64 = run_batched(S.BT_FP64, args.batch_wave)
     log(f"[bench] fp64 batched: {fp64}")
     # plain RGF: FP64, one instance at a time, one launch per block product, one stream
-    nplain = min(len(specs), args.plain_count)
+    nplain = len(specs) if args.plain_count < 0 else min(len(specs), args.plain_count)
     t_plain = 0.0
     for i in range(nplain):
         sp = specs[i]
@@ -235,6 +235,8 @@ def bench_batch(args, torch, S):
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t0
         sol.destroy()
+        if (i + 1) % 64 == 0:
+            log(f"[bench] plain RGF: {i + 1} of {nplain} instances, {t_plain:.1f} s timed")
     plain = dict(solves_per_s=round(nplain / t_plain, 3), instances=nplain)
     log(f"[bench] plain RGF: {plain}")
     out = {
@@ -336,7 +338,8 @@ def main():
                     help="1: pick product tile shapes with the autotuner before timing")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-wave", type=int, default=32)
-    ap.add_argument("--plain-count", type=int, default=8)
+    ap.add_argument("--plain-count", type=int, default=-1,
+                    help="instances of the batch timed with plain RGF (-1: all of them)")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--unsaturated-factor", type=float, default=0.7,
                     help="serve: also replay the trace at this fraction of the measured capacity (0: skip)")
