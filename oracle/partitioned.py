@@ -19,10 +19,13 @@ elimination order.  The per-block step is the Schur-complement step of
 rgf.forward_step / rgf.backward_step.
 
 With reduced_split=True a reduced system of at least four blocks is itself
-solved by this partitioned elimination with two partitions (its first half
-top-down, its second half bottom-up, each with its own tip contribution,
-then its two middle blocks and the tip): the same selected blocks in exact
-arithmetic, in another order.
+solved by this partitioned elimination (the recursive call of Sec. III-B):
+with reduced_parts = 2 (the default) by two partitions, its first half
+top-down and its second half bottom-up, each with its own tip contribution,
+then its two middle blocks and the tip; with reduced_parts = Q > 2 by
+q = min(Q, m // 2) partitions of an m-block reduced system, first, middle and
+last as above, whose own reduced system is solved the same way in turn.
+Every order gives the same selected blocks in exact arithmetic.
 """
 from __future__ import annotations
 
@@ -139,7 +142,14 @@ def reduced_system(A, B, bounds):
     return Ar, Br, reduced
 
 
-def prgf(A, B, bounds, reduced_split=False):
+def reduced_bounds(m, parts):
+    """Partition bounds of an m-block reduced system split into
+    q = min(parts, m // 2) contiguous parts of near-equal length."""
+    q = max(2, min(parts, m // 2))
+    return [i * m // q for i in range(q + 1)]
+
+
+def prgf(A, B, bounds, reduced_split=False, reduced_parts=2):
     """Partitioned SI (+ SQ when B is given).  Returns (X^R, X^<) as Sel.
     Blocks may differ in size (Sec. II-A)."""
     sizes = block_sizes(A)
@@ -158,7 +168,8 @@ def prgf(A, B, bounds, reduced_split=False):
     Br = _Reduced(Bt, reduced, a) if quad else None
     m = len(reduced)
     if reduced_split and m >= 4:
-        YR, YL = prgf(Ar, Br, [0, m // 2, m])
+        YR, YL = prgf(Ar, Br, reduced_bounds(m, reduced_parts), reduced_split=reduced_parts > 2,
+                      reduced_parts=reduced_parts)
     else:
         YR, YL = rgf_bta(Ar, Br)
     for Y, X in ((YR, XR), (YL, XL)) if quad else ((YR, XR),):

@@ -332,3 +332,38 @@ def test_reduced_split_runs_another_order():
     XR0, XL0 = oracle.solve_dense(A, B)
     assert rel_err(XR2, XR0) < 1e-11 and rel_err(XL2, XL0) < 1e-10
     assert rel_err(XR1, XR0) < 1e-11 and rel_err(XL1, XL0) < 1e-10
+
+
+@pytest.mark.parametrize("n,b,a", [(8, 1, 0), (10, 2, 0), (9, 2, 2), (12, 1, 3)])
+@pytest.mark.parametrize("parts", [3, 4])
+def test_recursive_reduced_solve_brute_force(n, b, a, parts):
+    """The reduced system solved by the partitioned elimination with `parts`
+    partitions, recursively (Sec. III-B): over every admissible partition of
+    tiny inputs into P = 4 or 5 parts (reduced systems of 6 and 8 blocks),
+    against the dense definition."""
+    A, B = gen_problem(n, b, a, E=0.2, eta=1e-2, seed=n * 10 + b + a + parts)
+    XR0, XL0 = oracle.solve_dense(A, B)
+    seen = 0
+    for P in (4, 5):
+        for bounds in _all_bounds(n, P):
+            XR, XL = oracle.prgf(A, B, bounds, reduced_split=True, reduced_parts=parts)
+            assert rel_err(XR, XR0) < 1e-11
+            assert rel_err(XL, XL0) < 1e-10
+            seen += 1
+    assert seen >= 3
+
+
+def test_recursive_reduced_solve_is_another_order():
+    """With three parts the reduced system (10 blocks) is split three ways and
+    its own reduced system (4 blocks) two ways: a different order from the
+    two-way split, the same selected blocks."""
+    A, B = gen_problem(14, 4, 2, E=0.2, eta=1e-2, seed=5)
+    bounds = [0, 2, 4, 6, 8, 10, 14]            # reduced system of 10 blocks
+    assert oracle.partitioned.reduced_bounds(10, 3) == [0, 3, 6, 10]
+    assert oracle.partitioned.reduced_bounds(10, 2) == [0, 5, 10]
+    XR2, XL2 = oracle.prgf(A, B, bounds, reduced_split=True)
+    XR3, XL3 = oracle.prgf(A, B, bounds, reduced_split=True, reduced_parts=3)
+    assert not np.array_equal(np.asarray(XR2.diag), np.asarray(XR3.diag))
+    XR0, XL0 = oracle.solve_dense(A, B)
+    for XR, XL in ((XR2, XL2), (XR3, XL3)):
+        assert rel_err(XR, XR0) < 1e-11 and rel_err(XL, XL0) < 1e-10
