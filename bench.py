@@ -355,6 +355,9 @@ def main():
     ap.add_argument("--antihermitian", type=int, default=1,
                     help="1: also time the reported form with BT_SIGMA_ANTIHERMITIAN (the synthetic "
                          "Sigma^< is anti-Hermitian) and report it beside the value")
+    ap.add_argument("--reduced-parts", type=int, nargs="*", default=[],
+                    help="also time each named partitioned form with its reduced system solved by the "
+                         "partitioned scheme with this many parts, recursively (reported, not the value)")
     ap.add_argument("--probe-max-tflop", type=float, default=2.0,
                     help="serving: largest request (TFLOP) spent on probing the mixed path")
     args = ap.parse_args()
@@ -433,16 +436,19 @@ def main():
     # forms: (key, partitions, extra flags); with blocks and tip of at most
     # 64 the sequential sweep also runs as one fused launch (BT_FUSED)
     fusable = max(sizes or [b]) <= 64 and a <= 64
-    variants = [(f"P{q}", q, 0) for q in forms + extra]
+    # (key, partitions, flags, reduced_parts); 0 = the library's default split
+    variants = [(f"P{q}", q, 0, 0) for q in forms + extra]
     if fusable and args.fused:
-        variants.append(("P1_fused", 1, S.BT_FUSED))
-    named = [k for k, q, _ in variants if q in forms]
+        variants.append(("P1_fused", 1, S.BT_FUSED, 0))
+    named = [k for k, q, _, r in variants if q in forms and r == 0]
+    variants += [(f"P{q}_reduced{r}", q, 0, r) for q in forms if q >= 3 for r in args.reduced_parts]
     timed = {}
-    for key, q, fl in variants:
-        sol = S.Solver(n, b, a, partitions=q, flags=args.flags | fl, sizes=sizes)
+    for key, q, fl, r in variants:
+        sol = S.Solver(n, b, a, partitions=q, flags=args.flags | fl, sizes=sizes, reduced_parts=r)
         el, lt = time_solves(torch, sol, dA, dB, XR, XL, args.steps, args.warmup)
-        exP, usP = S.flops(n, b, a, q, sizes=sizes)
-        timed[key] = dict(P=q, flags=fl, elapsed=el, lat=lt, launches=sol.last_launch_count(), ex=exP, us=usP)
+        exP, usP = S.flops(n, b, a, q, sizes=sizes, reduced_parts=r)
+        timed[key] = dict(P=q, flags=fl, reduced_parts=r, elapsed=el, lat=lt,
+                          launches=sol.last_launch_count(), ex=exP, us=usP)
         sol.destroy()
         log(f"[bench] {key}: {1e3 * el / args.steps:.2f} ms/solve, {timed[key]['launches']} launches/solve")
     best = min(named, key=lambda k: timed[k]["elapsed"])
@@ -501,12 +507,13 @@ def main():
     def form_entry(k):
         t = timed[k]
         sec = t["elapsed"] / args.steps
+        extra_keys = {"reduced_parts": t["reduced_parts"]} if t["reduced_parts"] else {}
         return dict(partitions=t["P"], fused=bool(t["flags"]), solves_per_s=round(args.steps / t["elapsed"], 4),
                     ms_per_step=round(1e3 * sec, 3), launches=t["launches"],
                     pct_fp64_peak_executed=round(100 * t["ex"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
                     pct_fp64_peak_useful=round(100 * t["us"] / sec / 1e12 / FP64_PEAK_TFLOPS, 2),
-                    latency_ms=latency_summary(t["lat"]))
-    compare = {k: form_entry(k) for k, _, _ in variants if k != best}
+                    latency_ms=latency_summary(t["lat"]), **extra_keys)
+    compare = {k: form_entry(k) for k, _, _, _ in variants if k != best}
 
     # the same form with the anti-Hermitian Sigma^< option (not the value: it
     # assumes the structure of the input), with its difference to the general path

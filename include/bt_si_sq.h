@@ -140,6 +140,16 @@ typedef struct {
                                    or NULL for n blocks of size b.  RGF applies
                                    unchanged to blocks of different sizes (Sec. II-A);
                                    b is then ignored.  Read during the call only. */
+    int32_t reduced_parts;      /* P > 1: the reduced system (2(P-1) kept blocks and the
+                                   tip) is solved by the same partitioned elimination,
+                                   recursively (Sec. III-B), with
+                                   q = min(reduced_parts, m/2) parts of an m-block
+                                   reduced system while m >= 4, then the sequential
+                                   RGF.  0 (default) = 2: first half top-down, second
+                                   half bottom-up; 1 = sequential RGF at once.  More
+                                   parts shorten the sequential chain but add the middle
+                                   parts' fill, which with an arrowhead also amplifies
+                                   rounding.  0..1024, else BT_ERR_INVALID. */
 } bt_desc;
 
 typedef struct {

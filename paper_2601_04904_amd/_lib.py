@@ -39,7 +39,7 @@ class bt_desc(C.Structure):
     _fields_ = [("n", C.c_int32), ("b", C.c_int32), ("a", C.c_int32),
                 ("partitions", C.c_int32), ("part_bounds", C.POINTER(C.c_int32)),
                 ("precision", C.c_int32), ("tol", C.c_double), ("flags", C.c_uint32),
-                ("block_sizes", C.POINTER(C.c_int32))]
+                ("block_sizes", C.POINTER(C.c_int32)), ("reduced_parts", C.c_int32)]
 
 
 class bt_blocks(C.Structure):
@@ -152,8 +152,11 @@ def lib():
 
 
 def make_desc(n: int, b: int, a: int = 0, partitions: int = 1, bounds=None,
-              precision: int = BT_FP64, tol: float = 1e-4, flags: int = 0, sizes=None):
-    """bt_desc; sizes: per-block sizes (then b is ignored) or None."""
+              precision: int = BT_FP64, tol: float = 1e-4, flags: int = 0, sizes=None,
+              reduced_parts: int = 0):
+    """bt_desc; sizes: per-block sizes (then b is ignored) or None;
+    reduced_parts: parts of the reduced system's recursive partitioned solve
+    (0: the default two)."""
     d = bt_desc()
     d.n, d.b, d.a, d.partitions = n, b, a, partitions
     keep = None
@@ -167,6 +170,7 @@ def make_desc(n: int, b: int, a: int = 0, partitions: int = 1, bounds=None,
         keep_sizes = (C.c_int32 * n)(*[int(v) for v in sizes])
         d.block_sizes = C.cast(keep_sizes, C.POINTER(C.c_int32))
     d.precision, d.tol, d.flags = precision, tol, flags
+    d.reduced_parts = reduced_parts
     d._keep = (keep, keep_sizes)  # keep the arrays alive with the descriptor
     return d
 

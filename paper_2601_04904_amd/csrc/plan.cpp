@@ -316,6 +316,7 @@ struct Builder {
                               // only where the backward sweep reads them again)
     std::unordered_set<uint64_t> needX;   // pairs (u, v) some backward step reads: N(k) x N(k)
     int instance = 0;     // instance id within a batch (reported with singular blocks)
+    int reduced_parts = 2;    // partitions of the reduced system's own partitioned solve
     MatRef Ib, Ia;        // identity blocks (filled once at create)
     MatRef norm_out;      // norms written by the check (5 per block row)
 
@@ -729,69 +730,81 @@ struct Builder {
         }
     }
 
+    // The reduced system: the kept blocks R (consecutive entries coupled, by an
+    // original or a fill block) plus the tip, itself a BT(A) matrix.  With at
+    // least four blocks it is solved by the same partitioned elimination
+    // (the recursive call of Sec. III-B) with q = min(reduced_parts, m / 2)
+    // contiguous parts of near-equal length: the first top-down, the last
+    // bottom-up, the middle ones top-down against their top block with fill,
+    // each adding its tip contribution to an accumulator of its own (summed
+    // into the tip afterwards); their kept blocks form the next reduced
+    // system, solved the same way.  With two parts it is its first half
+    // top-down and its second half bottom-up, concurrent, then the two middle
+    // blocks and the tip: the sequential chain shrinks from m to m/2 + 1
+    // inverses.  Below four blocks: the sequential BTA RGF.
+    void solve_reduced(const std::vector<int>& R, int& next_tag) {
+        const int t = D.n;
+        const bool arrow = D.a > 0;
+        const int m = (int)R.size();
+        if (m < 4 || reduced_parts < 2) {
+            std::vector<StepRec> red;
+            for (int j = 0; j < m; ++j) {
+                std::vector<int> N;
+                if (j + 1 < m) N.push_back(R[j + 1]);
+                if (arrow) N.push_back(t);
+                red.push_back(forward(R[j], N, 0, true));
+            }
+            if (arrow) red.push_back(forward(t, {}, 0, true));
+            for (auto it = red.rbegin(); it != red.rend(); ++it) backward(*it);
+            return;
+        }
+        const int q = std::max(2, std::min(reduced_parts, m / 2));
+        std::vector<std::vector<StepRec>> parts(q);
+        std::vector<int> R2, tags;
+        for (int p = 0; p < q; ++p) {
+            const int s = p * m / q, e = (p + 1) * m / q - 1;
+            const int tag = next_tag++;
+            tags.push_back(tag);
+            auto with_tip = [&](std::vector<int> N) { if (arrow) N.push_back(t); return N; };
+            if (p == 0) {
+                for (int j = s; j < e; ++j) parts[p].push_back(forward(R[j], with_tip({R[j + 1]}), tag, true));
+                R2.push_back(R[e]);
+            } else if (p == q - 1) {
+                for (int j = e; j > s; --j) parts[p].push_back(forward(R[j], with_tip({R[j - 1]}), tag, true));
+                R2.push_back(R[s]);
+            } else {
+                for (int j = s + 1; j < e; ++j)
+                    parts[p].push_back(forward(R[j], with_tip({R[s], R[j + 1]}), tag, true));
+                R2.push_back(R[s]);
+                R2.push_back(R[e]);
+            }
+        }
+        if (arrow) sum_tip(tags);
+        solve_reduced(R2, next_tag);
+        for (auto& part : parts)
+            for (auto it = part.rbegin(); it != part.rend(); ++it) backward(*it);
+    }
+
     void build() {
         Ib = alloc(D.b, D.b);
         Ia = alloc(std::max(D.a, 1), std::max(D.a, 1));
         init_stores();
         PlanShape ps = make_plan(D, bounds);
         const int P = (int)bounds.size() - 1;
-        const int t = D.n;
         const bool arrow = D.a > 0;
         std::vector<std::vector<StepRec>> recs(ps.parts.size());
         for (size_t p = 0; p < ps.parts.size(); ++p) {
             const int tag = (P > 1) ? (int)p + 1 : 0;
             for (auto& e : ps.parts[p]) recs[p].push_back(forward(e.k, e.N, tag, false));
         }
-        std::vector<StepRec> red;
         if (P > 1) {
             if (arrow) {
                 std::vector<int> tags;
                 for (int p = 0; p < P; ++p) tags.push_back(p + 1);
                 sum_tip(tags);
             }
-            const auto& R = ps.reduced;
-            const size_t m = R.size();
-            if (m >= 4) {
-                // The reduced system is itself a BT(A) matrix; it is split like
-                // a two-partition solve: its first half eliminated top-down, its
-                // second half bottom-up (concurrently: the halves touch
-                // disjoint blocks and create no fill; each adds its tip
-                // contribution to an accumulator of its own, summed into the
-                // tip afterwards), then the two middle blocks and the tip in
-                // sequence.  Its sequential chain shrinks from m to m/2 + 1
-                // inverses (+ the tip).
-                const size_t h = m / 2;
-                const int tag_top = P + 1, tag_bot = P + 2;
-                std::vector<StepRec> top, bot, mid;
-                for (size_t j = 0; j + 1 < h; ++j) {
-                    std::vector<int> N{R[j + 1]};
-                    if (arrow) N.push_back(t);
-                    top.push_back(forward(R[j], N, tag_top, true));
-                }
-                for (size_t j = m - 1; j > h; --j) {
-                    std::vector<int> N{R[j - 1]};
-                    if (arrow) N.push_back(t);
-                    bot.push_back(forward(R[j], N, tag_bot, true));
-                }
-                if (arrow) sum_tip({tag_top, tag_bot});
-                std::vector<int> N1{R[h]}, N2;
-                if (arrow) { N1.push_back(t); N2.push_back(t); }
-                mid.push_back(forward(R[h - 1], N1, 0, true));
-                mid.push_back(forward(R[h], N2, 0, true));
-                if (arrow) mid.push_back(forward(t, {}, 0, true));
-                for (auto it = mid.rbegin(); it != mid.rend(); ++it) backward(*it);
-                for (auto it = top.rbegin(); it != top.rend(); ++it) backward(*it);
-                for (auto it = bot.rbegin(); it != bot.rend(); ++it) backward(*it);
-            } else {
-                for (size_t j = 0; j < m; ++j) {
-                    std::vector<int> N;
-                    if (j + 1 < m) N.push_back(R[j + 1]);
-                    if (arrow) N.push_back(t);
-                    red.push_back(forward(R[j], N, 0, true));
-                }
-                if (arrow) red.push_back(forward(t, {}, 0, true));
-                for (auto it = red.rbegin(); it != red.rend(); ++it) backward(*it);
-            }
+            int next_tag = P + 1;
+            solve_reduced(ps.reduced, next_tag);
         }
         for (size_t p = 0; p < recs.size(); ++p)
             for (auto it = recs[p].rbegin(); it != recs[p].rend(); ++it) backward(*it);
@@ -1358,6 +1371,10 @@ bool desc_bounds(const bt_desc* d, std::vector<int>& bounds, std::string& msg) {
     }
     const int P = d->partitions;
     if (P < 1) { msg = "partitions must be >= 1"; return false; }
+    if (d->reduced_parts < 0 || d->reduced_parts > 1024) {
+        msg = "reduced_parts must lie in 0..1024";
+        return false;
+    }
     Dims D(d->n, d->b, d->a, d->block_sizes);
     if (d->part_bounds) {
         bounds.assign(d->part_bounds, d->part_bounds + P + 1);
@@ -1394,6 +1411,7 @@ bool build_instances(std::vector<Instance>& inst, const std::vector<int>& sel, M
         Builder bd;
         bd.D = I.D;
         bd.bounds = I.bounds;
+        bd.reduced_parts = I.desc.reduced_parts > 0 ? I.desc.reduced_parts : 2;
         bd.mode = mode;
         const bool mixed_handle = I.desc.precision == BT_MIXED;
         bd.mixed_bulk = mixed_handle && !fp64_rerun;

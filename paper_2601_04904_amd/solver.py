@@ -148,8 +148,9 @@ class VarDeviceBlocks:
         return bl
 
 
-def workspace_bytes(n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, sizes=None) -> int:
-    d = make_desc(n, b, a, partitions, bounds, precision, sizes=sizes)
+def workspace_bytes(n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, sizes=None,
+                    reduced_parts=0) -> int:
+    d = make_desc(n, b, a, partitions, bounds, precision, sizes=sizes, reduced_parts=reduced_parts)
     return int(_lib.lib().bt_si_sq_workspace_bytes(C.byref(d)))
 
 
@@ -160,9 +161,9 @@ def partition_bounds(n, b, a=0, partitions=1, bounds=None, sizes=None):
     return list(out)
 
 
-def flops(n, b, a=0, partitions=1, bounds=None, flags=0, sizes=None):
+def flops(n, b, a=0, partitions=1, bounds=None, flags=0, sizes=None, reduced_parts=0):
     """(executed, useful) real flops of one fused SI+SQ solve."""
-    d = make_desc(n, b, a, partitions, bounds, flags=flags, sizes=sizes)
+    d = make_desc(n, b, a, partitions, bounds, flags=flags, sizes=sizes, reduced_parts=reduced_parts)
     ex, us = C.c_double(), C.c_double()
     check(_lib.lib().bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)))
     return ex.value, us.value
@@ -179,10 +180,10 @@ class Solver:
     """
 
     def __init__(self, n, b, a=0, partitions=1, bounds=None, precision=BT_FP64, tol=1e-4,
-                 stream=None, flags=0, sizes=None):
+                 stream=None, flags=0, sizes=None, reduced_parts=0):
         torch = _torch()
         self.n, self.b, self.a = n, b, a
-        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol, flags, sizes)
+        self._desc = make_desc(n, b, a, partitions, bounds, precision, tol, flags, sizes, reduced_parts)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         check(_lib.lib().bt_si_sq_create(C.byref(self._desc), C.c_void_p(self.stream.cuda_stream),
@@ -262,7 +263,7 @@ class BatchSolver:
         self.count = len(specs)
         self._descs = [make_desc(sp["n"], sp.get("b", 0), sp.get("a", 0), sp.get("partitions", 1),
                                  sp.get("bounds"), sp.get("precision", BT_FP64), sp.get("tol", 1e-4),
-                                 sp.get("flags", 0), sp.get("sizes"))
+                                 sp.get("flags", 0), sp.get("sizes"), sp.get("reduced_parts", 0))
                        for sp in specs]
         arr = (_lib.bt_desc * self.count)(*self._descs)
         self._arr = arr
@@ -330,7 +331,7 @@ class BatchSolver:
 def batch_workspace_bytes(specs) -> int:
     descs = [make_desc(sp["n"], sp.get("b", 0), sp.get("a", 0), sp.get("partitions", 1), sp.get("bounds"),
                        sp.get("precision", BT_FP64), sp.get("tol", 1e-4), sp.get("flags", 0),
-                       sp.get("sizes")) for sp in specs]
+                       sp.get("sizes"), sp.get("reduced_parts", 0)) for sp in specs]
     arr = (_lib.bt_desc * len(descs))(*descs)
     return int(_lib.lib().bt_si_sq_batch_workspace_bytes(len(descs), arr))
 

@@ -111,6 +111,25 @@ def _flops(n, b, a, P, bounds=None):
     return ex.value, us.value
 
 
+def step(dk, Ns):
+    D = sum(Ns)
+    f = 8 * dk ** 3                              # inverse
+    f += 8 * dk * dk * D                         # T_u
+    f += 8 * D * D * dk                          # A updates
+    f += 16 * dk ** 3                            # S_B
+    f += 8 * dk * dk * D                         # W_u
+    f += 3 * 8 * D * D * dk                      # B updates
+    f += 8 * dk * dk * D + 8 * D * D * dk        # tau, rho
+    f += 8 * D * dk * dk + 8 * dk * D * D        # X_uk, X_kv
+    f += 8 * D * dk * dk                         # X_kk
+    f += 8 * D * D * dk * 2                      # GB, BG
+    f += 2 * 8 * D * dk * dk                     # Y21
+    f += 2 * 8 * dk * dk * D + 8 * dk * D * D    # L_kv (Y12 + update)
+    f += 8 * D * D * dk                          # L_uk
+    f += 2 * 8 * dk * dk * D                     # L_kk
+    return f
+
+
 @pytest.mark.parametrize("n,b,a", [(1, 8, 0), (2, 8, 0), (16, 32, 0), (64, 512, 0), (5, 7, 3),
                                    (128, 384, 512)])
 def test_flop_model_sequential(n, b, a):
@@ -118,24 +137,6 @@ def test_flop_model_sequential(n, b, a):
     inverse 8b^3 + products 8(2b^3 + 11Db^2 + 10D^2 b) (counted independently here)."""
     ex, us = _flops(n, b, a, 1)
     assert ex == us
-
-    def step(dk, Ns):
-        D = sum(Ns)
-        f = 8 * dk ** 3                              # inverse
-        f += 8 * dk * dk * D                         # T_u
-        f += 8 * D * D * dk                          # A updates
-        f += 16 * dk ** 3                            # S_B
-        f += 8 * dk * dk * D                         # W_u
-        f += 3 * 8 * D * D * dk                      # B updates
-        f += 8 * dk * dk * D + 8 * D * D * dk        # tau, rho
-        f += 8 * D * dk * dk + 8 * dk * D * D        # X_uk, X_kv
-        f += 8 * D * dk * dk                         # X_kk
-        f += 8 * D * D * dk * 2                      # GB, BG
-        f += 2 * 8 * D * dk * dk                     # Y21
-        f += 2 * 8 * dk * dk * D + 8 * dk * D * D    # L_kv (Y12 + update)
-        f += 8 * D * D * dk                          # L_uk
-        f += 2 * 8 * dk * dk * D                     # L_kk
-        return f
 
     ref = 0
     for k in range(n):
@@ -152,6 +153,52 @@ def test_flop_model_partitioned_executes_more():
     ex, us = _flops(64, 512, 0, 8)
     assert us == pytest.approx(192 * 63 * 512 ** 3 + 24 * 512 ** 3)
     assert 1.5 < ex / us < 1.8
+
+
+def _partitioned_neighbour_counts(n, bounds, Q):
+    """Neighbour counts of every elimination of the partitioned scheme on a BT
+    matrix (Sec. III-B): first partition top-down and last bottom-up with one
+    neighbour, middle ones against their top block with two; the 2(P - 1)
+    kept blocks are then solved by the same scheme with Q parts while they
+    number at least four (Q < 2: sequentially)."""
+    P = len(bounds) - 1
+    counts = []
+    for p in range(P):
+        s, e = bounds[p], bounds[p + 1]
+        counts += [1] * (e - s - 1) if p in (0, P - 1) else [2] * (e - s - 2)
+    m = 2 * (P - 1)
+    while m >= 4 and Q >= 2:
+        q = max(2, min(Q, m // 2))
+        for p in range(q):
+            s, e = p * m // q, (p + 1) * m // q - 1
+            counts += [1] * (e - s) if p in (0, q - 1) else [2] * (e - s - 1)
+        m = 2 * (q - 1)
+    return counts + [1] * (m - 1) + [0]
+
+
+@pytest.mark.parametrize("n,P,Q", [(64, 16, 0), (64, 16, 1), (64, 16, 3), (64, 16, 4), (64, 16, 9),
+                                   (40, 20, 1024), (12, 3, 5)])
+def test_flop_model_recursive_reduced_solve(n, P, Q):
+    from paper_2601_04904_amd.solver import partition_bounds
+    b = 16
+    bounds = partition_bounds(n, b, 0, P)
+    d = make_desc(n, b, 0, P, bounds, reduced_parts=Q)
+    ex, us = C.c_double(), C.c_double()
+    assert _lib.lib().bt_si_sq_flops(C.byref(d), C.byref(ex), C.byref(us)) == BT_OK
+    counts = _partitioned_neighbour_counts(n, bounds, 2 if Q == 0 else Q)
+    assert len(counts) == n
+    assert ex.value == pytest.approx(sum(step(b, [b] * c) for c in counts), rel=1e-12)
+    assert us.value == pytest.approx(192 * (n - 1) * b ** 3 + 24 * b ** 3, rel=1e-12)
+
+
+@pytest.mark.parametrize("Q", [-1, 1025])
+def test_reduced_parts_out_of_range_rejected(Q):
+    d = make_desc(16, 8, 0, 4, reduced_parts=Q)
+    assert _lib.lib().bt_si_sq_workspace_bytes(C.byref(d)) == 0
+    h = C.c_void_p()
+    assert _lib.lib().bt_si_sq_create(C.byref(d), None, C.byref(h)) == BT_ERR_INVALID
+    msg = _lib.lib().bt_si_sq_last_error(None)
+    assert "reduced_parts" in (msg.decode() if isinstance(msg, bytes) else msg)
 
 
 def test_workspace_bytes_scales():

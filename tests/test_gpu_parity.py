@@ -88,6 +88,52 @@ def run_flags(S, A, B, partitions, flags):
     return out
 
 
+REDUCED_CASES = [
+    # n, b, a, partitions, reduced_parts (reduced system of 2(P - 1) blocks)
+    (24, 16, 0, 9, 1),
+    (24, 16, 0, 9, 3),
+    (24, 16, 0, 9, 4),
+    (30, 12, 20, 12, 3),
+    (40, 8, 12, 16, 4),
+    (40, 8, 12, 16, 8),
+    (48, 6, 10, 24, 1024),
+    (18, 9, 5, 9, 5),
+]
+
+
+@pytest.mark.parametrize("n,b,a,P,Q", REDUCED_CASES)
+def test_recursive_reduced_solve_parity(S, n, b, a, P, Q):
+    """The reduced system solved by the partitioned scheme with Q parts,
+    recursively (Sec. III-B), against the dense inverse and against the
+    oracle's partitioned solve in the same order of elimination.
+
+    Broadening 0.05: the partitioned orders eliminate without pivoting across
+    blocks, and at 1e-3 the oracle's own partitioned solve of several of these
+    small instances is 1e-9 to 3e-8 away from the dense inverse (rounding
+    amplified by near-singular Schur complements of the middle parts), which
+    is the method's conditioning, not the kernels'.  At 0.05 it is at most 2e-13."""
+    print(f"case reduced_parts n={n} b={b} a={a} P={P} Q={Q}", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=0.05, seed=70 + n + b + a + P + Q)
+    R0, L0 = oracle.solve_dense(A, B)
+    bounds = S.partition_bounds(n, b, a, P)
+    if Q == 1:
+        R1, L1 = oracle.prgf(A, B, bounds)
+    else:
+        R1, L1 = oracle.prgf(A, B, bounds, reduced_split=True, reduced_parts=Q)
+    dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
+    XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
+    sol = S.Solver(n, b, a, partitions=P, bounds=bounds, reduced_parts=Q)
+    sol.solve(dA, dB, XR, XL)
+    sol.sync()
+    XR, XL = XR.to_host(), XL.to_host()
+    sol.destroy()
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    oR, oL = rel_err(XR, R1), rel_err(XL, L1)
+    print(f"  err vs dense R={eR:.3e} L={eL:.3e}; vs same-order oracle R={oR:.3e} L={oL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL
+    assert oR < TOL and oL < TOL
+
+
 @pytest.mark.parametrize("n,b,a,P", [(12, 40, 0, 1), (14, 33, 0, 3), (9, 36, 20, 1), (10, 28, 24, 2)])
 def test_plain_schedule_parity(S, n, b, a, P):
     """BT_PLAIN, the one-launch-per-product reference schedule behind every
