@@ -147,6 +147,10 @@ __device__ void step_panel(const InvJob& J, int p, int tid, DevStatus* status) {
     const int d = J.d;
     const int j0 = p * NB;
     if (j0 >= d) return;
+    // The panel's column chain is the critical path of the whole inverse and
+    // is latency-bound; where product workgroups of the other stream share
+    // this CU, their waves would otherwise take most of the issue slots.
+    __builtin_amdgcn_s_setprio(3);
     const int nc = min(NB, d - j0);
     const int lane = tid & 63, wave = tid >> 6;
     const double2* src = block_source(J, p, p);
