@@ -107,3 +107,25 @@ def test_batch_with_caller_workspace_matches_library_allocation(S):
     for (A, B), (xr, xl) in zip(probs, outs[0]):
         R0, L0 = oracle.solve_dense(A, B)
         assert rel_err(xr, R0) < 1e-11 and rel_err(xl, L0) < 1e-11
+
+
+def test_batch_instance_with_recursive_reduced_solve(S):
+    """An instance whose reduced system is split into three parts recursively
+    (Sec. III-B) in a batch with others: against the oracle's partitioned solve
+    in the same order, and bitwise equal to the same instance solved alone."""
+    specs = [dict(n=24, b=16, a=0, partitions=9, reduced_parts=3),
+             dict(n=10, b=40, a=12, partitions=2), dict(n=30, b=12, a=20, partitions=12, reduced_parts=4)]
+    problems = [gen_problem(sp["n"], sp["b"], sp["a"], E=0.3, eta=0.05, seed=200 + i)
+                for i, sp in enumerate(specs)]
+    out, err, fb = _solve_batch(S, specs, problems)
+    for sp, (A, B), (XR, XL) in zip(specs, problems, out):
+        bounds = S.partition_bounds(sp["n"], sp["b"], sp["a"], sp["partitions"])
+        q = sp.get("reduced_parts", 0)
+        R1, L1 = oracle.prgf(A, B, bounds, reduced_split=True, reduced_parts=q if q else 2)
+        eR, eL = rel_err(XR, R1), rel_err(XL, L1)
+        print(sp, f"R={eR:.2e} L={eL:.2e}", flush=True)
+        assert eR < 1e-11 and eL < 1e-11
+    alone, _, _ = _solve_batch(S, [specs[2]], [problems[2]])
+    for f in FIELDS:
+        assert np.array_equal(getattr(alone[0][0], f), getattr(out[2][0], f)), f
+        assert np.array_equal(getattr(alone[0][1], f), getattr(out[2][1], f)), f

@@ -27,11 +27,12 @@ def S():
     return solver
 
 
-def run(S, A, B, P=1, bounds=None, flags=0, split=False):
+def run(S, A, B, P=1, bounds=None, flags=0, split=False, reduced_parts=0):
     n, b, a = A.diag.shape[0], A.diag.shape[1], A.tip.shape[0]
     dA, dB = S.DeviceBlocks.from_host(A), S.DeviceBlocks.from_host(B)
     XR, XL = S.DeviceBlocks.empty(n, b, a), S.DeviceBlocks.empty(n, b, a)
-    sol = S.Solver(n, b, a, partitions=P, bounds=bounds, flags=S.BT_FUSED | flags)
+    sol = S.Solver(n, b, a, partitions=P, bounds=bounds, flags=S.BT_FUSED | flags,
+                   reduced_parts=reduced_parts)
     if split:
         sol.factor(dA, XR)
         sol.selected_solve(dB, XL)
@@ -70,6 +71,25 @@ def test_fused_parity(S, n, b, a, P, bounds):
     eR, eL = rel_err(XR, R0), rel_err(XL, L0)
     print(f"  err R={eR:.3e} L={eL:.3e} launches={launches}", flush=True)
     assert eR < TOL and eL < TOL
+    assert launches == 1
+
+
+@pytest.mark.parametrize("n,b,a,P,Q", [(24, 16, 0, 9, 3), (30, 12, 20, 12, 4)])
+def test_fused_recursive_reduced_solve(S, n, b, a, P, Q):
+    """The reduced system split into Q parts recursively (Sec. III-B) inside
+    the one-workgroup executor, against the dense definition and against the
+    oracle's partitioned solve in the same order (broadening 0.05: at 1e-3 the
+    partitioned order's own rounding on such inputs exceeds the bar)."""
+    print(f"case BT_FUSED reduced_parts n={n} b={b} a={a} P={P} Q={Q}", flush=True)
+    A, B = gen_problem(n, b, a, E=0.3, eta=0.05, seed=90 + n + b + a + P + Q)
+    R0, L0 = oracle.solve_dense(A, B)
+    bounds = S.partition_bounds(n, b, a, P)
+    R1, L1 = oracle.prgf(A, B, bounds, reduced_split=True, reduced_parts=Q)
+    (XR, XL), launches = run(S, A, B, P, bounds, reduced_parts=Q)
+    eR, eL = rel_err(XR, R0), rel_err(XL, L0)
+    oR, oL = rel_err(XR, R1), rel_err(XL, L1)
+    print(f"  err R={eR:.3e} L={eL:.3e}; same order R={oR:.3e} L={oL:.3e}", flush=True)
+    assert eR < TOL and eL < TOL and oR < TOL and oL < TOL
     assert launches == 1
 
 
