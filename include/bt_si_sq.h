@@ -148,8 +148,9 @@ typedef struct {
                                    RGF.  0 (default) = 2: first half top-down, second
                                    half bottom-up; 1 = sequential RGF at once.  More
                                    parts shorten the sequential chain but add the middle
-                                   parts' fill, which with an arrowhead also amplifies
-                                   rounding.  0..1024, else BT_ERR_INVALID. */
+                                   parts' fill and flops, and on weakly broadened
+                                   inputs (no pivoting across blocks) amplify rounding.
+                                   0..1024, else BT_ERR_INVALID. */
 } bt_desc;
 
 typedef struct {
