@@ -50,7 +50,7 @@ __device__ inline const double2* block_source(const InvJob& J, int blk, int p) {
     return written ? J.W : J.src;
 }
 
-// Update workgroup u of launch p: its 16 columns take T_{p-1}; in the last
+// Update workgroup u of launch p: its kUpdCols columns take T_{p-1}; in the last
 // launch they are also written to the result.  It gathers the pivot rows of
 // panel p-1 restricted to its own columns first, so no workgroup reads what
 // another writes in the same launch.
@@ -366,7 +366,21 @@ void inv_step(const InvJob* __restrict__ jobs, int p, int wg_per_job, DevStatus*
     const int w = blockIdx.x - job * wg_per_job;
     const InvJob J = jobs[job];
     if (w == 0) step_panel<T, R>(J, p, threadIdx.x, status);
-    else step_update<T, R>(J, p, w - 1, threadIdx.x);
+    else {
+        // The two 8-column slabs of the next panel's block go to the update
+        // workgroups 8 and 16 of the job, whose ids are congruent to the panel
+        // workgroup's mod 8 (same XCD, same L2), so the next launch's panel
+        // workgroup reads them where they were written.  A bijection of the
+        // slab indices: two transpositions.
+        int u = w - 1;
+        const int nslab = wg_per_job - 1;
+        const int a = 2 * (p + 1), b = a + 1;
+        if (nslab > 15 && b < nslab) {
+            u = u == 7 ? a : u == a ? 7 : u;
+            u = u == 15 ? b : u == b ? 15 : u;
+        }
+        step_update<T, R>(J, p, u, threadIdx.x);
+    }
 }
 
 int inv_variant(int d) { return d <= 256 ? 0 : d <= 512 ? 1 : 2; }
