@@ -177,7 +177,7 @@ def _partitioned_neighbour_counts(n, bounds, Q):
 
 
 @pytest.mark.parametrize("n,P,Q", [(64, 16, 0), (64, 16, 1), (64, 16, 3), (64, 16, 4), (64, 16, 9),
-                                   (40, 20, 1024), (12, 3, 5)])
+                                   (40, 20, 1024), (12, 3, 5), (6, 3, 3), (10, 5, 4), (14, 7, 3)])
 def test_flop_model_recursive_reduced_solve(n, P, Q):
     from paper_2601_04904_amd.solver import partition_bounds
     b = 16

@@ -98,6 +98,13 @@ REDUCED_CASES = [
     (40, 8, 12, 16, 8),
     (48, 6, 10, 24, 1024),
     (18, 9, 5, 9, 5),
+    # at the recursion's limits: reduced systems of 4 to 12 blocks, middle parts
+    # of two blocks (nothing eliminated in them), a one-block first partition
+    (6, 8, 0, 3, 3),
+    (9, 10, 6, 4, 3),
+    (10, 12, 0, 5, 4),
+    (12, 9, 7, 5, 4),
+    (14, 8, 5, 7, 3),
 ]
 
 
